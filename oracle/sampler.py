@@ -1,0 +1,226 @@
+"""Red-black Metropolis sweep with sequential parameter moves (oracle, FP64).
+
+One sweep k follows Fig. 1 and Sections 4.1-4.2 of the paper:
+
+1. every even site n, then every odd site n (Fig. 2 and Section 4.1: sites
+   of one parity are uncoupled, so they may be updated in any order or
+   simultaneously): propose x_n' = x_n + w * z with all D components moved
+   jointly, reject if x_n' leaves the box (Section 4.2), else accept with
+   probability min(1, exp(-dA)) (Metropolis rule, Section 3.1);
+2. each sampled parameter p_l in ascending l (Fig. 1 step 3): propose
+   p_l' = p_l + w_l z, reject outside the box, else compute dA over the whole
+   path and accept with the same rule;
+3. statistics of the path after the burn-in (Section 4.1).
+
+Readings where the paper is silent or inconsistent:
+* colour order: Fig. 1 lists odd first, the text and Fig. 2 even first; even
+  first is taken (n = 0 is even);
+* proposal law: Gaussian z by default, the U(-1, 1) step of Fig. 1 as an
+  option;
+* "accept if U(0,1) < P_acc" is taken as: accept iff log u < -dA with
+  u = (c + 0.5) 2**-32 from the generator contract (so dA <= 0 always
+  accepts); a non-finite dA rejects and is counted;
+* the random numbers come from Philox at fixed logical addresses (see
+  `philox`) instead of a per-thread Tausworthe stream.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import philox as ph
+from .action import delta_params, delta_site
+
+STATES = 1
+PARAMS = 2
+
+ACC_EVEN, ACC_ODD, ACC_PARAM0, ACC_NONFINITE = 0, 1, 2, 9
+N_ACC = 10
+
+
+@dataclass
+class Stats:
+    """Shifted moments sum(x - xref), sum((x - xref)^2) over sweeps k >= burn,
+    the parameter vector after every sweep, and acceptance counters."""
+
+    M: int
+    D: int
+    Np: int
+    n_sweeps: int
+    burn: int = 0
+    xref: Optional[np.ndarray] = None
+    sum: np.ndarray = field(init=False)
+    sumsq: np.ndarray = field(init=False)
+    ptrace: np.ndarray = field(init=False)
+    acc: np.ndarray = field(init=False)
+    n_post: int = 0
+
+    def __post_init__(self):
+        self.sum = np.zeros((self.M + 1, self.D))
+        self.sumsq = np.zeros((self.M + 1, self.D))
+        self.ptrace = np.zeros((self.n_sweeps, self.Np))
+        self.acc = np.zeros(N_ACC, dtype=np.int64)
+
+
+@dataclass
+class Debug:
+    """What the last sweep proposed and decided (for lockstep comparisons)."""
+
+    xprop: Optional[np.ndarray] = None     # (M+1, D)
+    dA: Optional[np.ndarray] = None        # (M+1,), NaN where out of box
+    u: Optional[np.ndarray] = None         # (M+1,)
+    accept: Optional[np.ndarray] = None    # (M+1,) bool
+    pprop: Optional[np.ndarray] = None     # (Np,) proposed value of p_l
+    pdA: Optional[np.ndarray] = None       # (Np,)
+    pu: Optional[np.ndarray] = None        # (Np,)
+    paccept: Optional[np.ndarray] = None   # (Np,) bool
+
+
+def accepts(u, dA):
+    """Metropolis decision of Section 3.1: accept with probability
+    min(1, exp(-dA)), realised as log u < -dA for u uniform in (0, 1).
+    A non-finite dA never accepts."""
+    with np.errstate(invalid="ignore"):
+        return np.isfinite(dA) & (np.log(u) < -np.asarray(dA, dtype=np.float64))
+
+
+def site_draws(spec, seed, chain, k, ns):
+    """Proposal steps z (len(ns), D) and accept uniforms u for sites ns."""
+    ns = np.asarray(ns, dtype=np.int64)
+    blk = ph.draw(seed, chain, ns, k, ph.TAG_SITE)
+    if spec.proposal == "uniform":
+        z = ph.uniforms_pm1(blk)
+    else:
+        z = ph.normals4(blk)
+    acc = ph.draw(seed, chain, ns >> 2, k, ph.TAG_SACC)
+    u = ph.uniform_open(acc[np.arange(len(ns)), ns & 3])
+    return z[:, :spec.D], u
+
+
+def param_draw(spec, seed, chain, k, l):
+    """Proposal step z and accept uniform u of parameter l (0-based)."""
+    b = ph.draw(seed, chain, l, k, ph.TAG_PARAM)[0]
+    if spec.proposal == "uniform":
+        z = float(ph.uniforms_pm1(b[None, :])[0, 0])
+    else:
+        z = float(ph.box_muller(b[0], b[1])[0])
+    return z, float(ph.uniform_open(b[2]))
+
+
+def _in_box(x, lo, hi):
+    return ((x >= lo) & (x <= hi)).all(axis=-1)
+
+
+def color_update(spec, X, y, I, p, k, color, w_state, seed, chain, acc=None,
+                 order=None, debug: Optional[Debug] = None):
+    """Update every site of one parity (in place).
+
+    order=None evaluates the colour at once (legal because same-parity sites
+    are uncoupled); otherwise sites are visited one at a time in the given
+    permutation of the colour, each against the current path.
+    """
+    M = X.shape[0] - 1
+    ns = np.arange(color, M + 1, 2)
+    z, u = site_draws(spec, seed, chain, k, ns)
+    xprop = X[ns] + np.asarray(w_state)[None, :] * z
+    lo = np.asarray(spec.x_lo)
+    hi = np.asarray(spec.x_hi)
+    inbox = _in_box(xprop, lo, hi)
+    dA = np.full(len(ns), np.nan)
+    if order is None:
+        if inbox.any():
+            dA[inbox] = delta_site(spec, X, y, I, p, ns[inbox], xprop[inbox])
+        accept = inbox & accepts(u, dA)
+        X[ns[accept]] = xprop[accept]
+    else:
+        accept = np.zeros(len(ns), dtype=bool)
+        for i in order:
+            if not inbox[i]:
+                continue
+            dA[i] = delta_site(spec, X, y, I, p, ns[i:i + 1], xprop[i:i + 1])[0]
+            if accepts(u[i], dA[i]):
+                accept[i] = True
+                X[ns[i]] = xprop[i]
+    if acc is not None:
+        acc[ACC_EVEN + color] += int(accept.sum())
+        acc[ACC_NONFINITE] += int((inbox & ~np.isfinite(dA)).sum())
+    if debug is not None:
+        debug.xprop[ns] = xprop
+        debug.dA[ns] = dA
+        debug.u[ns] = u
+        debug.accept[ns] = accept
+    return accept
+
+
+def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
+                debug: Optional[Debug] = None):
+    """Sequential Metropolis moves of the sampled parameters (in place on p)."""
+    lo = np.asarray(spec.p_lo)
+    hi = np.asarray(spec.p_hi)
+    for l in range(len(p)):
+        if not (spec.p_mask >> l) & 1:
+            continue
+        z, u = param_draw(spec, seed, chain, k, l)
+        pp = p.copy()
+        pp[l] = p[l] + w_param[l] * z
+        dA = np.nan
+        ok = False
+        if lo[l] <= pp[l] <= hi[l]:
+            dA = delta_params(spec, X, I, p, pp)
+            ok = bool(accepts(u, dA))
+            if not np.isfinite(dA) and acc is not None:
+                acc[ACC_NONFINITE] += 1
+        if ok:
+            p[l] = pp[l]
+            if acc is not None:
+                acc[ACC_PARAM0 + l] += 1
+        if debug is not None:
+            debug.pprop[l] = pp[l]
+            debug.pdA[l] = dA
+            debug.pu[l] = u
+            debug.paccept[l] = ok
+
+
+def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
+        flags=STATES | PARAMS, stats: Optional[Stats] = None,
+        debug: Optional[Debug] = None, order_rng: Optional[np.random.Generator] = None):
+    """n_sweeps sweeps k = sweep0 .. sweep0 + n_sweeps - 1, in place on X, p.
+
+    debug, if given, is filled for the last sweep of the call.
+    order_rng, if given, visits the sites of each colour in a random order.
+    """
+    M = X.shape[0] - 1
+    acc = stats.acc if stats is not None else None
+    for i in range(n_sweeps):
+        k = sweep0 + i
+        dbg = debug if (debug is not None and i == n_sweeps - 1) else None
+        if dbg is not None:
+            D = X.shape[1]
+            dbg.xprop = np.full((M + 1, D), np.nan)
+            dbg.dA = np.full(M + 1, np.nan)
+            dbg.u = np.full(M + 1, np.nan)
+            dbg.accept = np.zeros(M + 1, dtype=bool)
+            dbg.pprop = np.full(len(p), np.nan)
+            dbg.pdA = np.full(len(p), np.nan)
+            dbg.pu = np.full(len(p), np.nan)
+            dbg.paccept = np.zeros(len(p), dtype=bool)
+        if flags & STATES:
+            for color in (0, 1):
+                order = None
+                if order_rng is not None:
+                    order = order_rng.permutation(len(range(color, M + 1, 2)))
+                color_update(spec, X, y, I, p, k, color, w_state, seed, chain,
+                             acc=acc, order=order, debug=dbg)
+        if flags & PARAMS:
+            param_moves(spec, X, I, p, k, w_param, seed, chain, acc=acc, debug=dbg)
+        if stats is not None:
+            stats.ptrace[i] = p
+            if k >= stats.burn:
+                d = X - (stats.xref if stats.xref is not None else 0.0)
+                stats.sum += d
+                stats.sumsq += d * d
+                stats.n_post += 1
+    return X, p

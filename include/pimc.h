@@ -1,0 +1,207 @@
+/*
+ * libpimc -- path-integral Monte Carlo data assimilation on AMD MI355X (gfx950).
+ *
+ * The library samples the posterior exp(-A(X, p)) over the whole discretised
+ * state history X = {x_0 .. x_M} of a Hodgkin-Huxley neuron and its
+ * parameters p, following Quinn & Abarbanel, "Data Assimilation using a GPU
+ * Accelerated Path Integral Monte Carlo Approach" (arXiv:1103.4887):
+ *
+ *   A = A_o + beta A_d                                   (Section 2.1)
+ *   A_o = 1/2 sum_{n=1..M} Ro (y_n - V_n)^2              (observation error)
+ *   A_d = 1/2 sum_{n=1..M} eps_n^T Rd eps_n              (model error)
+ *   eps_n = x_n - x_{n-1} - dt/2 [F(x_n; p) + F(x_{n-1}; p)]   (trapezoid rule)
+ *
+ * with the HH vector field F of Section 5.1 (dV/dt and da/dt equations,
+ * gating constants of Table 1) and a uniform box prior on states and
+ * parameters (Section 2.1, Section 4.2).
+ *
+ * Conventions for every entry point:
+ *  - all array pointers are caller-owned DEVICE memory unless stated; the
+ *    library never frees or retains them;
+ *  - `stream` is a hipStream_t (NULL = the default stream); every call is
+ *    asynchronous on it;
+ *  - argument errors are detected on the host before anything is enqueued and
+ *    return a negative pimc_status; a problem found on the device (a state or
+ *    parameter outside its box at entry, a non-finite action change) sets a
+ *    flag in the context that the next pimc_sync() reports;
+ *  - a path holds M+1 sites; X is [M+1][4] row-major in the order (V, m, h, n)
+ *    in FP64 (PIMC_FP64) or FP32 (PIMC_FP32); y and I are [M+1] in the same
+ *    precision, y[0] is never read (observations start at n = 1);
+ *  - parameters p are FP64 [7] = (p1 .. p7) of the dV/dt equation.
+ *
+ * Random numbers are Philox4x32-10 (Salmon et al., SC'11) at fixed logical
+ * addresses: key = (seed_lo32, seed_hi32 ^ chain), counter = (index,
+ * sweep_lo32, tag << 24 | sweep_hi24, block).  Results therefore depend on
+ * (seed, chain, sweep index) only, never on launch shape.
+ */
+#ifndef PIMC_H
+#define PIMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIMC_OK = 0,
+  PIMC_ERR_ARG = -1,          /* invalid argument (null pointer, size, enum) */
+  PIMC_ERR_HIP = -2,          /* a HIP runtime call failed */
+  PIMC_ERR_NONFINITE = -3,    /* a non-finite action change was met (reported by pimc_sync) */
+  PIMC_ERR_UNSUPPORTED = -4,  /* shape not supported by the built kernels */
+  PIMC_ERR_NOMEM = -5,        /* workspace allocation failed */
+  PIMC_ERR_BOX = -6           /* state or parameter outside its box at entry (reported by pimc_sync) */
+} pimc_status;
+
+enum { PIMC_FP64 = 0, PIMC_FP32 = 1 };          /* site arithmetic precision */
+enum { PIMC_PROP_GAUSS = 0, PIMC_PROP_UNIFORM = 1 }; /* proposal law (Fig. 1 step 1a = uniform) */
+enum { PIMC_STATES = 1, PIMC_PARAMS = 2 };       /* pimc_sweep flags */
+
+/* acceptance counters written to pimc_stats.acc */
+enum { PIMC_ACC_EVEN = 0, PIMC_ACC_ODD = 1, PIMC_ACC_PARAM0 = 2, PIMC_ACC_NONFINITE = 9, PIMC_NACC = 10 };
+
+typedef struct pimc_ctx pimc_ctx;
+
+/* Model, noise precisions and box prior; host memory, copied at each call. */
+typedef struct {
+  double dt;          /* time step (ms) */
+  double Ro;          /* observation precision (L = 1, observed component V) */
+  double Rd[4];       /* diagonal model-error precision (V, m, h, n) */
+  double beta;        /* multiplier of A_d (annealing factor, Section 4.2) */
+  double Va[3], dVa[3], tau0[3], tau1[3];  /* Table 1, order (m, h, n) */
+  double x_lo[4], x_hi[4];                 /* state box, every site */
+  double p_lo[7], p_hi[7];                 /* parameter box */
+  uint32_t p_mask;    /* bit l set => p_{l+1} is sampled */
+  int32_t proposal;   /* PIMC_PROP_GAUSS or PIMC_PROP_UNIFORM */
+} pimc_model;
+
+/* One window.  X and p are read and written; y and I are read only. */
+typedef struct {
+  int64_t M;          /* number of steps; sites n = 0..M; M >= 1 */
+  int32_t prec;       /* PIMC_FP64 or PIMC_FP32: type of X, y, I */
+  void* X;            /* [M+1][4] */
+  double* p;          /* [7] FP64 */
+  const void* y;      /* [M+1], y[0] unused */
+  const void* I;      /* [M+1], drive at t_n */
+} pimc_path;
+
+/* Random-number address: sweep k of a call is sweep0 + (0 .. n_sweeps-1). */
+typedef struct {
+  uint64_t seed;
+  uint32_t chain;
+  uint64_t sweep0;
+} pimc_rng;
+
+/* Statistics (every pointer nullable; device memory).
+ *   sum, sumsq  [M+1][4] FP64, accumulated (+=) over sweeps k >= burn:
+ *               sum (x - xref) and sum (x - xref)^2
+ *   xref        [M+1][4] in path precision (required when sum/sumsq given)
+ *   ptrace      [n_sweeps][7] FP64: p after every sweep of the call (written)
+ *   acc         [PIMC_NACC] int64 acceptance counters (+=) */
+typedef struct {
+  double* sum;
+  double* sumsq;
+  const void* xref;
+  double* ptrace;
+  int64_t* acc;
+  int64_t burn;
+} pimc_stats;
+
+/* What the LAST sweep of a call proposed and decided (every pointer nullable).
+ *   xprop [M+1][4] path precision, dA [M+1] FP64 (NaN where the proposal left
+ *   the box), accept [M+1] uint8; pprop/pdA [7] FP64, paccept [7] uint8
+ *   (entries of unsampled parameters are left untouched). */
+typedef struct {
+  void* xprop;
+  double* dA;
+  uint8_t* accept;
+  double* pprop;
+  double* pdA;
+  uint8_t* paccept;
+} pimc_debug;
+
+/* Packed batch of independent windows for pimc_run_batch.
+ *   offsets   HOST [B+1]: window w owns packed sites offsets[w] .. offsets[w+1]-1,
+ *             so M_w = offsets[w+1] - offsets[w] - 1 >= 1
+ *   X [S][4], y [S], I [S] packed in path precision (S = offsets[B])
+ *   p [B][7] FP64, chain [B] uint32 (Philox chain id of each window) */
+typedef struct {
+  int32_t B;
+  int32_t prec;
+  const int64_t* offsets;
+  void* X;
+  double* p;
+  const void* y;
+  const void* I;
+  const uint32_t* chain;
+} pimc_batch;
+
+/* Per-window statistics of a batch (every pointer nullable; device memory).
+ *   sum, sumsq [S][4] FP64 packed like X; xref [S][4] path precision;
+ *   ptrace [B][n_sweeps][7] FP64; acc [B][PIMC_NACC] int64. */
+typedef struct {
+  double* sum;
+  double* sumsq;
+  const void* xref;
+  double* ptrace;
+  int64_t* acc;
+  int64_t burn;
+} pimc_batch_stats;
+
+/* Create a context bound to HIP device `device` (it owns only its workspace:
+ * error flags, reduction scratch, captured graphs).  Returns PIMC_OK. */
+int pimc_ctx_create(pimc_ctx** out, int device);
+void pimc_ctx_destroy(pimc_ctx* ctx);
+
+/* Sites per thread of the sweep kernel: 4, 8 or 16 (FP32) / 4 or 8 (FP64);
+ * 0 restores the automatic choice.  The chain does not depend on it: random
+ * numbers are addressed by (site, sweep), never by thread. */
+int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
+
+/* Wait for `stream`, then return and clear any deferred device-side error
+ * (PIMC_ERR_BOX first, then PIMC_ERR_NONFINITE). */
+int pimc_sync(pimc_ctx* ctx, void* stream);
+
+const char* pimc_strerror(int status);
+
+/* Full action (Section 2.1): out3 (device, FP64 [3]) <- (A, A_o, A_d) with
+ * A = A_o + beta A_d.  Terms are evaluated in FP64 for either path precision
+ * and summed in a fixed order. */
+int pimc_action(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path,
+                double* out3, void* stream);
+
+/* n_sweeps red-black Metropolis sweeps (Fig. 1; Sections 3.1, 4.1-4.2):
+ * all even sites, then all odd sites (joint D-component proposal
+ * x' = x + w z, box test, accept iff log u < -dA with dA in FP64 for the
+ * decision), then -- if PIMC_PARAMS -- each sampled parameter in ascending
+ * order.  w: device FP64 [11] = proposal widths of (V, m, h, n) then
+ * (p1 .. p7).  stats and debug are nullable. */
+int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng,
+               const double* w, int64_t n_sweeps, int32_t flags,
+               const pimc_stats* stats, const pimc_debug* debug, void* stream);
+
+/* One round of sequential parameter moves (Fig. 1 step 3, Section 4.1) at
+ * sweep index rng.sweep0, with the path held fixed; identical to pimc_sweep
+ * with n_sweeps = 1 and flags = PIMC_PARAMS.  w as for pimc_sweep. */
+int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng,
+                      const double* w, const pimc_debug* debug, void* stream);
+
+/* Gradient of the action: gX [M+1][4] (path precision) <- dA/dX and
+ * gp [7] FP64 <- dA/dp, from the local stencil of the trapezoid model error
+ * (derivatives of A are what the force-bias / Hybrid Monte Carlo proposals
+ * mentioned in Section 3.1 need). */
+int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path,
+              void* gX, double* gp, void* stream);
+
+/* n_sweeps sweeps of every window of a packed batch in one launch.  All
+ * windows share model, seed and widths w (device FP64 [11]); window w uses
+ * Philox chain id batch->chain[w] and sweep indices sweep0 .. sweep0+n-1. */
+int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* batch,
+                   uint64_t seed, uint64_t sweep0, const double* w, int64_t n_sweeps,
+                   int32_t flags, const pimc_batch_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIMC_H */

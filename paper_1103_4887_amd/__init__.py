@@ -1,0 +1,15 @@
+"""libpimc for AMD MI355X: path-integral Monte Carlo data assimilation.
+
+Red-black Metropolis sweeps over the whole state history of a
+Hodgkin-Huxley neuron plus its parameters, after Quinn & Abarbanel,
+"Data Assimilation using a GPU Accelerated Path Integral Monte Carlo
+Approach" (arXiv:1103.4887).  The compute path is the HIP library
+libpimc.so (C ABI in include/pimc.h); this package only binds it.
+"""
+
+from . import _lib
+from .api import (Context, PackedBatch, SweepDebug, SweepStats, Window, model_struct, pimc_action,
+                  pimc_grad, pimc_param_update, pimc_run_batch, pimc_sweep, widths_tensor)
+
+__all__ = ["Context", "PackedBatch", "SweepDebug", "SweepStats", "Window", "model_struct", "pimc_action",
+           "pimc_grad", "pimc_param_update", "pimc_run_batch", "pimc_sweep", "widths_tensor", "_lib"]

@@ -1,0 +1,286 @@
+"""Python binding of libpimc with the C ABI's names.
+
+Every function marshals torch tensors (device memory) and the current HIP
+stream into the C calls; all arithmetic of the method runs in the library's
+kernels.  A model description is any object with the attributes of the
+pimc_model struct (dt, Ro, Rd, beta, gates = ((V_a, dV_a, tau0, tau1) for
+m, h, n), x_lo, x_hi, p_lo, p_hi, p_mask, proposal).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DTYPES = {"fp64": torch.float64, "fp32": torch.float32}
+PRECS = {"fp64": L.PIMC_FP64, "fp32": L.PIMC_FP32}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libpimc takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libpimc takes contiguous tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def model_struct(spec) -> L.Model:
+    m = L.Model()
+    m.dt = float(spec.dt)
+    m.Ro = float(spec.Ro)
+    for i in range(4):
+        m.Rd[i] = float(spec.Rd[i])
+        m.x_lo[i] = float(spec.x_lo[i])
+        m.x_hi[i] = float(spec.x_hi[i])
+    m.beta = float(spec.beta)
+    for g in range(3):
+        Va, dVa, t0, t1 = spec.gates[g]
+        m.Va[g], m.dVa[g], m.tau0[g], m.tau1[g] = float(Va), float(dVa), float(t0), float(t1)
+    for l in range(7):
+        m.p_lo[l] = float(spec.p_lo[l])
+        m.p_hi[l] = float(spec.p_hi[l])
+    m.p_mask = int(spec.p_mask)
+    m.proposal = L.PIMC_PROP_UNIFORM if spec.proposal == "uniform" else L.PIMC_PROP_GAUSS
+    return m
+
+
+class Context:
+    """A libpimc context on one HIP device (owns only its small workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        self.device = device
+        h = C.c_void_p()
+        L.check(self.lib.pimc_ctx_create(C.byref(h), device), "pimc_ctx_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.pimc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile(self, K: int):
+        L.check(self.lib.pimc_set_sweep_tile(self.h, int(K)), "pimc_set_sweep_tile")
+
+    def sync(self, stream=None) -> int:
+        """Wait for the stream; returns the deferred device status (0 = ok)."""
+        return int(self.lib.pimc_sync(self.h, _stream(stream)))
+
+
+@dataclass
+class Window:
+    """Device-resident window: X [M+1][4], p [7] FP64, y, I [M+1]."""
+
+    X: torch.Tensor
+    p: torch.Tensor
+    y: torch.Tensor
+    I: torch.Tensor
+    prec: str
+
+    @property
+    def M(self) -> int:
+        return self.X.shape[0] - 1
+
+    @staticmethod
+    def from_arrays(X, p, y, I, prec: str = "fp32", device: str = "cuda") -> "Window":
+        dt = DTYPES[prec]
+        return Window(X=torch.as_tensor(np.asarray(X), dtype=dt, device=device).contiguous(),
+                      p=torch.as_tensor(np.asarray(p), dtype=torch.float64, device=device).contiguous(),
+                      y=torch.as_tensor(np.asarray(y), dtype=dt, device=device).contiguous(),
+                      I=torch.as_tensor(np.asarray(I), dtype=dt, device=device).contiguous(),
+                      prec=prec)
+
+    def path_struct(self) -> L.Path:
+        pa = L.Path()
+        pa.M = self.M
+        pa.prec = PRECS[self.prec]
+        pa.X = _ptr(self.X)
+        pa.p = _ptr(self.p)
+        pa.y = _ptr(self.y)
+        pa.I = _ptr(self.I)
+        return pa
+
+
+@dataclass
+class SweepStats:
+    sum: Optional[torch.Tensor] = None
+    sumsq: Optional[torch.Tensor] = None
+    xref: Optional[torch.Tensor] = None
+    ptrace: Optional[torch.Tensor] = None
+    acc: Optional[torch.Tensor] = None
+    burn: int = 0
+
+    @staticmethod
+    def allocate(win: Window, n_sweeps: int, burn: int = 0, moments: bool = True, trace: bool = True):
+        dev = win.X.device
+        st = SweepStats(burn=burn)
+        if moments:
+            st.sum = torch.zeros((win.M + 1, 4), dtype=torch.float64, device=dev)
+            st.sumsq = torch.zeros_like(st.sum)
+            st.xref = win.X.clone()
+        if trace:
+            st.ptrace = torch.zeros((n_sweeps, 7), dtype=torch.float64, device=dev)
+        st.acc = torch.zeros(L.PIMC_NACC, dtype=torch.int64, device=dev)
+        return st
+
+    def struct(self) -> L.Stats:
+        s = L.Stats()
+        s.sum, s.sumsq, s.xref = _ptr(self.sum), _ptr(self.sumsq), _ptr(self.xref)
+        s.ptrace, s.acc = _ptr(self.ptrace), _ptr(self.acc)
+        s.burn = int(self.burn)
+        return s
+
+
+@dataclass
+class SweepDebug:
+    xprop: torch.Tensor
+    dA: torch.Tensor
+    accept: torch.Tensor
+    pprop: torch.Tensor
+    pdA: torch.Tensor
+    paccept: torch.Tensor
+
+    @staticmethod
+    def allocate(win: Window):
+        dev = win.X.device
+        nan = float("nan")
+        return SweepDebug(xprop=torch.full_like(win.X, nan),
+                          dA=torch.full((win.M + 1,), nan, dtype=torch.float64, device=dev),
+                          accept=torch.zeros(win.M + 1, dtype=torch.uint8, device=dev),
+                          pprop=torch.full((7,), nan, dtype=torch.float64, device=dev),
+                          pdA=torch.full((7,), nan, dtype=torch.float64, device=dev),
+                          paccept=torch.zeros(7, dtype=torch.uint8, device=dev))
+
+    def struct(self) -> L.Debug:
+        d = L.Debug()
+        d.xprop, d.dA, d.accept = _ptr(self.xprop), _ptr(self.dA), _ptr(self.accept)
+        d.pprop, d.pdA, d.paccept = _ptr(self.pprop), _ptr(self.pdA), _ptr(self.paccept)
+        return d
+
+
+def _rng(seed: int, chain: int, sweep0: int) -> L.Rng:
+    r = L.Rng()
+    r.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    r.chain = int(chain) & 0xFFFFFFFF
+    r.sweep0 = int(sweep0)
+    return r
+
+
+def widths_tensor(w_state: Sequence[float], w_param: Sequence[float], device="cuda") -> torch.Tensor:
+    return torch.tensor(list(w_state) + list(w_param), dtype=torch.float64, device=device)
+
+
+def pimc_action(ctx: Context, spec, win: Window, out3: Optional[torch.Tensor] = None, stream=None):
+    if out3 is None:
+        out3 = torch.empty(3, dtype=torch.float64, device=win.X.device)
+    m, pa = model_struct(spec), win.path_struct()
+    L.check(ctx.lib.pimc_action(ctx.h, C.byref(m), C.byref(pa), _ptr(out3), _stream(stream)), "pimc_action")
+    return out3
+
+
+def pimc_grad(ctx: Context, spec, win: Window, gX: Optional[torch.Tensor] = None,
+              gp: Optional[torch.Tensor] = None, stream=None):
+    if gX is None:
+        gX = torch.empty_like(win.X)
+    if gp is None:
+        gp = torch.empty(7, dtype=torch.float64, device=win.X.device)
+    m, pa = model_struct(spec), win.path_struct()
+    L.check(ctx.lib.pimc_grad(ctx.h, C.byref(m), C.byref(pa), _ptr(gX), _ptr(gp), _stream(stream)), "pimc_grad")
+    return gX, gp
+
+
+def pimc_sweep(ctx: Context, spec, win: Window, *, seed: int, chain: int, sweep0: int, w: torch.Tensor,
+               n_sweeps: int, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
+               stats: Optional[SweepStats] = None, debug: Optional[SweepDebug] = None, stream=None):
+    m, pa = model_struct(spec), win.path_struct()
+    st = C.byref(stats.struct()) if stats is not None else None
+    db = C.byref(debug.struct()) if debug is not None else None
+    L.check(ctx.lib.pimc_sweep(ctx.h, C.byref(m), C.byref(pa), _rng(seed, chain, sweep0), _ptr(w),
+                               int(n_sweeps), int(flags), st, db, _stream(stream)), "pimc_sweep")
+
+
+def pimc_param_update(ctx: Context, spec, win: Window, *, seed: int, chain: int, sweep0: int,
+                      w: torch.Tensor, debug: Optional[SweepDebug] = None, stream=None):
+    m, pa = model_struct(spec), win.path_struct()
+    db = C.byref(debug.struct()) if debug is not None else None
+    L.check(ctx.lib.pimc_param_update(ctx.h, C.byref(m), C.byref(pa), _rng(seed, chain, sweep0), _ptr(w),
+                                      db, _stream(stream)), "pimc_param_update")
+
+
+@dataclass
+class PackedBatch:
+    """Windows packed end to end: X [S][4], y, I [S], p [B][7], chain [B]."""
+
+    offsets: np.ndarray      # host int64 [B+1]
+    X: torch.Tensor
+    p: torch.Tensor
+    y: torch.Tensor
+    I: torch.Tensor
+    chain: torch.Tensor
+    prec: str
+
+    @property
+    def B(self) -> int:
+        return len(self.offsets) - 1
+
+    @staticmethod
+    def pack(Xs, ps, ys, Is, chains, prec: str = "fp32", device: str = "cuda") -> "PackedBatch":
+        dt = DTYPES[prec]
+        sizes = [len(X) for X in Xs]
+        off = np.zeros(len(Xs) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        return PackedBatch(
+            offsets=off,
+            X=torch.as_tensor(np.concatenate(Xs), dtype=dt, device=device).contiguous(),
+            p=torch.as_tensor(np.stack(ps), dtype=torch.float64, device=device).contiguous(),
+            y=torch.as_tensor(np.concatenate(ys), dtype=dt, device=device).contiguous(),
+            I=torch.as_tensor(np.concatenate(Is), dtype=dt, device=device).contiguous(),
+            chain=torch.as_tensor(np.asarray(chains, dtype=np.uint32).view(np.int32), device=device).contiguous(),
+            prec=prec)
+
+    def struct(self):
+        b = L.Batch()
+        b.B = self.B
+        b.prec = PRECS[self.prec]
+        self._off = (C.c_int64 * len(self.offsets))(*[int(v) for v in self.offsets])
+        b.offsets = C.cast(self._off, C.POINTER(C.c_int64))
+        b.X, b.p, b.y, b.I, b.chain = _ptr(self.X), _ptr(self.p), _ptr(self.y), _ptr(self.I), _ptr(self.chain)
+        return b
+
+    def window(self, w: int):
+        a, b = int(self.offsets[w]), int(self.offsets[w + 1])
+        return self.X[a:b], self.p[w], self.y[a:b], self.I[a:b]
+
+
+def pimc_run_batch(ctx: Context, spec, batch: PackedBatch, *, seed: int, sweep0: int, w: torch.Tensor,
+                   n_sweeps: int, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
+                   stats: Optional[SweepStats] = None, stream=None):
+    m = model_struct(spec)
+    b = batch.struct()
+    st = None
+    if stats is not None:
+        bs = L.BatchStats()
+        bs.sum, bs.sumsq, bs.xref = _ptr(stats.sum), _ptr(stats.sumsq), _ptr(stats.xref)
+        bs.ptrace, bs.acc, bs.burn = _ptr(stats.ptrace), _ptr(stats.acc), int(stats.burn)
+        st = C.byref(bs)
+    L.check(ctx.lib.pimc_run_batch(ctx.h, C.byref(m), C.byref(b), int(seed), int(sweep0), _ptr(w),
+                                   int(n_sweeps), int(flags), st, _stream(stream)), "pimc_run_batch")

@@ -1,0 +1,341 @@
+// C ABI of libpimc: argument checking, workspace, launch-shape choice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pimc.h"
+
+struct pimc_ctx {
+  int device = 0;
+  uint32_t* err = nullptr;        // device word of deferred error bits
+  double* partial = nullptr;      // field-kernel workspace
+  size_t partial_cap = 0;         // in doubles
+  int64_t* offsets = nullptr;     // batch offsets (device copy)
+  int32_t* order = nullptr;       // batch launch order (device)
+  size_t batch_cap = 0;           // in windows
+  int tile_K = 0;                 // 0 = automatic choice of sites per thread
+};
+
+namespace {
+
+using pimc::ModelArgs;
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? PIMC_OK : PIMC_ERR_HIP; }
+
+int model_args(const pimc_model* m, ModelArgs& a) {
+  if (!m) return PIMC_ERR_ARG;
+  if (!(m->dt > 0.0) || !(m->Ro >= 0.0) || !(m->beta >= 0.0)) return PIMC_ERR_ARG;
+  for (int c = 0; c < 4; ++c)
+    if (!(m->Rd[c] >= 0.0) || !(m->x_lo[c] <= m->x_hi[c])) return PIMC_ERR_ARG;
+  for (int l = 0; l < 7; ++l)
+    if (!(m->p_lo[l] <= m->p_hi[l])) return PIMC_ERR_ARG;
+  for (int g = 0; g < 3; ++g)
+    if (m->dVa[g] == 0.0 || !(m->tau0[g] > 0.0) || !(m->tau1[g] >= 0.0)) return PIMC_ERR_ARG;
+  if (m->proposal != PIMC_PROP_GAUSS && m->proposal != PIMC_PROP_UNIFORM) return PIMC_ERR_ARG;
+  if (m->p_mask & ~0x7Fu) return PIMC_ERR_ARG;
+  std::memset(&a, 0, sizeof(a));
+  a.dt = m->dt;
+  a.Ro = m->Ro;
+  a.beta = m->beta;
+  for (int c = 0; c < 4; ++c) {
+    a.Rd[c] = m->Rd[c];
+    a.x_lo[c] = m->x_lo[c];
+    a.x_hi[c] = m->x_hi[c];
+  }
+  for (int g = 0; g < 3; ++g) {
+    a.Va[g] = m->Va[g];
+    a.dVa[g] = m->dVa[g];
+    a.tau0[g] = m->tau0[g];
+    a.tau1[g] = m->tau1[g];
+  }
+  for (int l = 0; l < 7; ++l) {
+    a.p_lo[l] = m->p_lo[l];
+    a.p_hi[l] = m->p_hi[l];
+  }
+  a.p_mask = m->p_mask;
+  a.proposal = m->proposal;
+  return PIMC_OK;
+}
+
+int ensure_partial(pimc_ctx* ctx, size_t n) {
+  if (n <= ctx->partial_cap) return PIMC_OK;
+  if (ctx->partial) {
+    if (hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
+    (void)hipFree(ctx->partial);
+    ctx->partial = nullptr;
+    ctx->partial_cap = 0;
+  }
+  if (hipMalloc(&ctx->partial, n * sizeof(double)) != hipSuccess) return PIMC_ERR_NOMEM;
+  ctx->partial_cap = n;
+  return PIMC_OK;
+}
+
+int ensure_batch(pimc_ctx* ctx, size_t B) {
+  if (B <= ctx->batch_cap) return PIMC_OK;
+  if (ctx->offsets) {
+    if (hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
+    (void)hipFree(ctx->offsets);
+    (void)hipFree(ctx->order);
+    ctx->offsets = nullptr;
+    ctx->order = nullptr;
+    ctx->batch_cap = 0;
+  }
+  if (hipMalloc(&ctx->offsets, (B + 1) * sizeof(int64_t)) != hipSuccess) return PIMC_ERR_NOMEM;
+  if (hipMalloc(&ctx->order, B * sizeof(int32_t)) != hipSuccess) return PIMC_ERR_NOMEM;
+  ctx->batch_cap = B;
+  return PIMC_OK;
+}
+
+// Sites per thread: the smallest supported K whose thread count fits.
+int choose_K(const pimc_ctx* ctx, int64_t maxM, bool fp64, int& NT) {
+  static const int cand32[] = {4, 8, 16};
+  static const int cand64[] = {4, 8};
+  const int* cand = fp64 ? cand64 : cand32;
+  const int nc = fp64 ? 2 : 3;
+  for (int i = 0; i < nc; ++i) {
+    const int K = cand[i];
+    if (ctx->tile_K && ctx->tile_K != K) continue;
+    const int64_t need = (maxM + K - 1) / K;
+    const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
+    if (nt <= pimc::sweep_max_threads(fp64, K)) {
+      NT = (int)nt;
+      return K;
+    }
+  }
+  return 0;
+}
+
+void fill_debug(pimc::SweepArgs& a, const pimc_debug* d) {
+  if (!d) return;
+  a.dbg_xprop = d->xprop;
+  a.dbg_dA = d->dA;
+  a.dbg_acc = d->accept;
+  a.dbg_pprop = d->pprop;
+  a.dbg_pdA = d->pdA;
+  a.dbg_pacc = d->paccept;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimc_ctx_create(pimc_ctx** out, int device) {
+  if (!out) return PIMC_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PIMC_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PIMC_ERR_HIP;
+  pimc_ctx* c = new (std::nothrow) pimc_ctx();
+  if (!c) return PIMC_ERR_NOMEM;
+  c->device = device;
+  if (hipMalloc(&c->err, sizeof(uint32_t)) != hipSuccess) {
+    delete c;
+    return PIMC_ERR_NOMEM;
+  }
+  if (hipMemset(c->err, 0, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(c->err);
+    delete c;
+    return PIMC_ERR_HIP;
+  }
+  if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
+  *out = c;
+  return PIMC_OK;
+}
+
+void pimc_ctx_destroy(pimc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->err) (void)hipFree(ctx->err);
+  if (ctx->partial) (void)hipFree(ctx->partial);
+  if (ctx->offsets) (void)hipFree(ctx->offsets);
+  if (ctx->order) (void)hipFree(ctx->order);
+  delete ctx;
+}
+
+int pimc_set_sweep_tile(pimc_ctx* ctx, int K) {
+  if (!ctx || !(K == 0 || K == 4 || K == 8 || K == 16)) return PIMC_ERR_ARG;
+  ctx->tile_K = K;
+  return PIMC_OK;
+}
+
+int pimc_sync(pimc_ctx* ctx, void* stream) {
+  if (!ctx) return PIMC_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PIMC_ERR_HIP;
+  uint32_t e = 0;
+  if (hipMemcpy(&e, ctx->err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess) return PIMC_ERR_HIP;
+  if (e) {
+    if (hipMemset(ctx->err, 0, sizeof(uint32_t)) != hipSuccess) return PIMC_ERR_HIP;
+    return (e & 2u) ? PIMC_ERR_BOX : PIMC_ERR_NONFINITE;
+  }
+  return PIMC_OK;
+}
+
+const char* pimc_strerror(int s) {
+  switch (s) {
+    case PIMC_OK: return "ok";
+    case PIMC_ERR_ARG: return "invalid argument";
+    case PIMC_ERR_HIP: return "HIP runtime error";
+    case PIMC_ERR_NONFINITE: return "non-finite action change encountered";
+    case PIMC_ERR_UNSUPPORTED: return "shape not supported by the built kernels";
+    case PIMC_ERR_NOMEM: return "out of device memory";
+    case PIMC_ERR_BOX: return "state or parameter outside its box at entry";
+    default: return "unknown status";
+  }
+}
+
+int pimc_action(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, double* out3, void* stream) {
+  if (!ctx || !path || !out3 || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
+  if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  pimc::FieldArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  const int64_t nb = pimc::field_blocks(path->M);
+  if ((r = ensure_partial(ctx, (size_t)nb * 8))) return r;
+  a.M = path->M;
+  a.X = path->X;
+  a.p = path->p;
+  a.y = path->y;
+  a.I = path->I;
+  a.partial = ctx->partial;
+  a.out = out3;
+  return pimc::launch_action(a, path->prec == PIMC_FP64, (hipStream_t)stream);
+}
+
+int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, void* gX, double* gp, void* stream) {
+  if (!ctx || !path || !gX || !gp || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
+  if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  pimc::FieldArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  const int64_t nb = pimc::field_blocks(path->M);
+  if ((r = ensure_partial(ctx, (size_t)nb * 8))) return r;
+  a.M = path->M;
+  a.X = path->X;
+  a.p = path->p;
+  a.y = path->y;
+  a.I = path->I;
+  a.gX = gX;
+  a.partial = ctx->partial;
+  a.out = gp;
+  return pimc::launch_grad(a, path->prec == PIMC_FP64, (hipStream_t)stream);
+}
+
+int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
+               int64_t n_sweeps, int32_t flags, const pimc_stats* stats, const pimc_debug* debug, void* stream) {
+  if (!ctx || !path || !w || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
+  if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
+  if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
+  if (n_sweeps == 0) return PIMC_OK;
+  pimc::SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  const bool fp64 = path->prec == PIMC_FP64;
+  int NT = 0;
+  const int K = choose_K(ctx, path->M, fp64, NT);
+  if (!K) return PIMC_ERR_UNSUPPORTED;
+  a.offsets = nullptr;
+  a.M_single = path->M;
+  a.X = path->X;
+  a.p = path->p;
+  a.y = path->y;
+  a.I = path->I;
+  a.chain_single = rng.chain;
+  a.seed = rng.seed;
+  a.sweep0 = rng.sweep0;
+  a.n_sweeps = n_sweeps;
+  a.flags = flags;
+  a.w = w;
+  if (stats) {
+    a.sum = stats->sum;
+    a.sumsq = stats->sumsq;
+    a.xref = stats->xref;
+    a.ptrace = stats->ptrace;
+    a.acc = stats->acc;
+    a.burn = stats->burn;
+  }
+  fill_debug(a, debug);
+  a.err = ctx->err;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  return pimc::launch_sweep(a, fp64, K, 1, NT, (hipStream_t)stream);
+}
+
+int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
+                      const pimc_debug* debug, void* stream) {
+  return pimc_sweep(ctx, model, path, rng, w, 1, PIMC_PARAMS, nullptr, debug, stream);
+}
+
+int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, uint64_t seed, uint64_t sweep0,
+                   const double* w, int64_t n_sweeps, int32_t flags, const pimc_batch_stats* stats, void* stream) {
+  if (!ctx || !b || !w || !b->offsets || !b->X || !b->p || !b->y || !b->I || !b->chain) return PIMC_ERR_ARG;
+  if (b->B < 1 || (b->prec != PIMC_FP64 && b->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
+  if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
+  if (n_sweeps == 0) return PIMC_OK;
+  const int B = b->B;
+  if (b->offsets[0] != 0) return PIMC_ERR_ARG;
+  int64_t maxM = 0;
+  std::vector<int64_t> Ms(B);
+  for (int i = 0; i < B; ++i) {
+    const int64_t Mi = b->offsets[i + 1] - b->offsets[i] - 1;
+    if (Mi < 1) return PIMC_ERR_ARG;
+    Ms[i] = Mi;
+    maxM = std::max(maxM, Mi);
+  }
+  pimc::SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  const bool fp64 = b->prec == PIMC_FP64;
+  int NT = 0;
+  const int K = choose_K(ctx, maxM, fp64, NT);
+  if (!K) return PIMC_ERR_UNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  if ((r = ensure_batch(ctx, (size_t)B))) return r;
+  // longest windows first, so the tail of the launch holds the short ones
+  std::vector<int32_t> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return Ms[x] > Ms[y]; });
+  hipStream_t s = (hipStream_t)stream;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->offsets, b->offsets, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s))))
+    return r;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->order, order.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, s))))
+    return r;
+  // the host vectors die at return: make sure the copies have consumed them
+  if ((r = hip_ok(hipStreamSynchronize(s)))) return r;
+  a.offsets = ctx->offsets;
+  a.order = ctx->order;
+  a.X = b->X;
+  a.p = b->p;
+  a.y = b->y;
+  a.I = b->I;
+  a.chain_ids = b->chain;
+  a.seed = seed;
+  a.sweep0 = sweep0;
+  a.n_sweeps = n_sweeps;
+  a.flags = flags;
+  a.w = w;
+  if (stats) {
+    a.sum = stats->sum;
+    a.sumsq = stats->sumsq;
+    a.xref = stats->xref;
+    a.ptrace = stats->ptrace;
+    a.acc = stats->acc;
+    a.burn = stats->burn;
+  }
+  a.err = ctx->err;
+  return pimc::launch_sweep(a, fp64, K, B, NT, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Kernel argument blocks and launchers shared by the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace pimc {
+
+struct SweepArgs {
+  ModelArgs m;
+  // windows: offsets == nullptr means one window of M_single + 1 sites
+  const int64_t* offsets;
+  const int32_t* order;  // block -> window map (nullable: identity)
+  int64_t M_single;
+  void* X;
+  double* p;
+  const void* y;
+  const void* I;
+  const uint32_t* chain_ids;
+  uint32_t chain_single;
+  uint64_t seed;
+  uint64_t sweep0;
+  int64_t n_sweeps;
+  int32_t flags;
+  const double* w;  // [11]
+  // statistics (nullable)
+  double* sum;
+  double* sumsq;
+  const void* xref;
+  double* ptrace;
+  int64_t* acc;
+  int64_t burn;
+  // last-sweep debug record (nullable)
+  void* dbg_xprop;
+  double* dbg_dA;
+  uint8_t* dbg_acc;
+  double* dbg_pprop;
+  double* dbg_pdA;
+  uint8_t* dbg_pacc;
+  uint32_t* err;  // bit 0: non-finite dA met, bit 1: entry state outside box
+};
+
+size_t sweep_smem_bytes(int NT, bool fp64);
+int sweep_max_threads(bool fp64, int K);
+int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s);
+
+struct FieldArgs {  // action / gradient of one window
+  ModelArgs m;
+  int64_t M;
+  const void* X;
+  const double* p;
+  const void* y;
+  const void* I;
+  void* gX;         // gradient output (path precision), nullable
+  double* partial;  // [nblocks][8] workspace
+  double* out;      // action: [3]; gradient: gp [7]
+};
+
+constexpr int FIELD_BLOCK = 256;
+int launch_action(const FieldArgs& a, bool fp64, hipStream_t s);
+int launch_grad(const FieldArgs& a, bool fp64, hipStream_t s);
+inline int64_t field_blocks(int64_t M) { return (M + 1 + FIELD_BLOCK - 1) / FIELD_BLOCK; }
+
+}  // namespace pimc

@@ -1,0 +1,309 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Tolerances (written per test):
+  * FP64 site arithmetic: per-site dA within 1e-12 * max(1, |dA|) of the
+    oracle's, accept decisions identical wherever |dA + log u| > 1e-6;
+  * FP32 site arithmetic: dA evaluated by the oracle on the GPU's own
+    proposal within 1e-4 * max(1, |dA|); decisions identical wherever
+    |dA + log u| > 1e-4 * max(1, |dA|);
+  * action: FP64 terms in both precisions -> 1e-12 relative;
+  * parameter moves: the GPU's sufficient-statistic dA equals the oracle's
+    direct sum over the path to 1e-9 relative (FP64 sums on both sides);
+  * integer work (acceptance counters, decisions away from ties): exact.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import action as OA
+from oracle import sampler as OS
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1103_4887_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _problem(M, seed=101, init="guess", mask=0x7F, proposal="gauss", dt=0.02):
+    spec = W.ModelSpec(dt=dt, p_mask=mask, proposal=proposal)
+    prob = W.make_hh_problem(M, dt, seed, model=spec, require_spike=False, init=init)
+    return prob
+
+
+def _perturbed(prob, seed=0):
+    """A state off the truth (a realistic mid-run path), inside the box."""
+    rng = np.random.default_rng(seed)
+    X = prob.X_true + rng.normal(size=prob.X_true.shape) * np.array([0.3, 2e-3, 2e-3, 2e-3])
+    X[:, 1:] = np.clip(X[:, 1:], 0.0, 1.0)
+    return X
+
+
+def _oracle_one_sweep(prob, X, p, sweep, chain=0, flags=3):
+    X = X.copy()
+    p = p.copy()
+    dbg = OS.Debug()
+    st = OS.Stats(prob.M, 4, 7, 1)
+    OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=chain, sweep0=sweep, n_sweeps=1,
+           w_state=prob.w_state, w_param=prob.w_param, flags=flags, stats=st, debug=dbg)
+    return X, p, dbg, st
+
+
+def _gpu_one_sweep(ctx, prob, X, p, sweep, prec, chain=0, flags=3):
+    win = P.Window.from_arrays(X, p, prob.y, prob.I, prec)
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    dbg = P.SweepDebug.allocate(win)
+    st = P.SweepStats.allocate(win, 1, moments=False)
+    print(f"gpu sweep prec={prec} M={prob.M} sweep={sweep} flags={flags}", flush=True)
+    P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=chain, sweep0=sweep, w=w, n_sweeps=1,
+                 flags=flags, stats=st, debug=dbg)
+    assert ctx.sync() == 0
+    return win, dbg, st
+
+
+@pytest.mark.parametrize("M", [1, 2, 7, 8, 9, 37, 256, 300])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_action_matches_oracle(ctx, M, prec):
+    prob = _problem(M)
+    X = _perturbed(prob)
+    if prec == "fp32":
+        X = X.astype(np.float32).astype(np.float64)
+    spec = prob.model.with_(beta=0.7)
+    win = P.Window.from_arrays(X, prob.p0, prob.y, prob.I, prec)
+    out = P.pimc_action(ctx, spec, win).cpu().numpy()
+    y = prob.y.astype(np.float32).astype(np.float64) if prec == "fp32" else prob.y
+    I = prob.I.astype(np.float32).astype(np.float64) if prec == "fp32" else prob.I
+    ref = OA.action(spec, X, y, I, prob.p0)
+    np.testing.assert_allclose(out, ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("M", [1, 5, 255, 256, 300])
+def test_grad_matches_oracle_fp64(ctx, M):
+    prob = _problem(M)
+    X = _perturbed(prob, 1)
+    spec = prob.model.with_(beta=0.9)
+    win = P.Window.from_arrays(X, prob.p0, prob.y, prob.I, "fp64")
+    gX, gp = P.pimc_grad(ctx, spec, win)
+    g_ref, gp_ref = OA.grad(spec, X, prob.y, prob.I, prob.p0)
+    scale = np.abs(g_ref).max()
+    np.testing.assert_allclose(gX.cpu().numpy(), g_ref, rtol=1e-10, atol=1e-12 * scale)
+    np.testing.assert_allclose(gp.cpu().numpy(), gp_ref, rtol=1e-9, atol=1e-12 * np.abs(gp_ref).max())
+
+
+def test_grad_fp32_close_to_oracle(ctx):
+    prob = _problem(300)
+    X = _perturbed(prob, 2).astype(np.float32).astype(np.float64)
+    win = P.Window.from_arrays(X, prob.p0, prob.y, prob.I, "fp32")
+    gX, gp = P.pimc_grad(ctx, prob.model, win)
+    y32 = prob.y.astype(np.float32).astype(np.float64)
+    I32 = prob.I.astype(np.float32).astype(np.float64)
+    g_ref, gp_ref = OA.grad(prob.model, X, y32, I32, prob.p0)
+    err = np.abs(gX.cpu().numpy() - g_ref) / (np.abs(g_ref) + 1e-3 * np.abs(g_ref).max(axis=0))
+    assert np.quantile(err, 0.99) < 1e-3
+    np.testing.assert_allclose(gp.cpu().numpy(), gp_ref, rtol=2e-3)
+
+
+def _check_sites(gdbg, odbg, tol, margin_of):
+    gdA = gdbg.dA.cpu().numpy()
+    gacc = gdbg.accept.cpu().numpy().astype(bool)
+    fin_g = np.isfinite(gdA)
+    fin_o = np.isfinite(odbg.dA)
+    assert np.array_equal(fin_g, fin_o), np.nonzero(fin_g != fin_o)
+    err = np.abs(gdA[fin_o] - odbg.dA[fin_o]) / np.maximum(1.0, np.abs(odbg.dA[fin_o]))
+    assert err.max() <= tol, err.max()
+    margin = np.abs(odbg.dA + np.log(odbg.u))
+    safe = ~fin_o | (margin > margin_of(odbg.dA))
+    assert np.array_equal(gacc[safe], odbg.accept[safe])
+    return int((~safe).sum())
+
+
+@pytest.mark.parametrize("M", [1, 2, 8, 9, 37, 256, 300, 1000, 4096])
+def test_sweep_fp64_lockstep(ctx, M):
+    prob = _problem(M)
+    X = _perturbed(prob, 3)
+    p = prob.p_true * 1.01
+    for sweep in (0, 12345678901):
+        Xo, po, od, so = _oracle_one_sweep(prob, X, p, sweep)
+        win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, sweep, "fp64")
+        np.testing.assert_allclose(gd.xprop.cpu().numpy(), od.xprop, rtol=1e-14, atol=1e-14)
+        ties = _check_sites(gd, od, 1e-12, lambda d: 1e-6)
+        gpdA = gd.pdA.cpu().numpy()
+        m = np.isfinite(od.pdA)
+        np.testing.assert_array_equal(np.isfinite(gpdA), m)
+        np.testing.assert_allclose(gpdA[m], od.pdA[m], rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(gd.pprop.cpu().numpy()[m], od.pprop[m], rtol=1e-15)
+        if ties == 0:
+            np.testing.assert_allclose(win.X.cpu().numpy(), Xo, rtol=1e-13, atol=1e-13)
+            np.testing.assert_allclose(win.p.cpu().numpy(), po, rtol=1e-14)
+            np.testing.assert_array_equal(gs.acc.cpu().numpy(), so.acc)
+
+
+@pytest.mark.parametrize("M", [8, 37, 256, 4096, 8192])
+def test_sweep_fp32_site_parity(ctx, M):
+    prob = _problem(M)
+    X = _perturbed(prob, 4).astype(np.float32).astype(np.float64)
+    p = prob.p_true * 0.99
+    y32 = prob.y.astype(np.float32).astype(np.float64)
+    I32 = prob.I.astype(np.float32).astype(np.float64)
+    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 77, "fp32", flags=P._lib.PIMC_STATES)
+    xp = gd.xprop.cpu().numpy().astype(np.float64)
+    # proposals: same Philox words, FP32 Box-Muller vs FP64
+    Xo, po, od, so = _oracle_one_sweep(prob, X, p, 77, flags=OS.STATES)
+    np.testing.assert_allclose(xp, od.xprop, rtol=2e-6, atol=2e-6 * np.abs(prob.w_state).max() * 10)
+    # dA of the GPU's own proposal, re-evaluated by the oracle on the same state
+    M1 = prob.M + 1
+    gdA = gd.dA.cpu().numpy()
+    gacc = gd.accept.cpu().numpy().astype(bool)
+    ref = np.full(M1, np.nan)
+    lo, hi = np.asarray(prob.model.x_lo), np.asarray(prob.model.x_hi)
+    Xcur = X.copy()
+    for color in (0, 1):
+        ns = np.arange(color, M1, 2)
+        inb = ((xp[ns] >= lo) & (xp[ns] <= hi)).all(axis=1)
+        d = np.full(len(ns), np.nan)
+        if inb.any():
+            d[inb] = OA.delta_site(prob.model, Xcur, y32, I32, p, ns[inb], xp[ns][inb])
+        ref[ns] = d
+        acc_n = ns[gacc[ns]]
+        Xcur[acc_n] = xp[acc_n]
+    fin = np.isfinite(ref)
+    np.testing.assert_array_equal(np.isfinite(gdA), fin)
+    err = np.abs(gdA[fin] - ref[fin]) / np.maximum(1.0, np.abs(ref[fin]))
+    assert err.max() <= 1e-4, err.max()
+    u = od.u
+    margin = np.abs(ref + np.log(u))
+    safe = fin & (margin > 1e-4 * np.maximum(1.0, np.abs(ref)))
+    decide = np.log(u) < -ref
+    np.testing.assert_array_equal(gacc[safe], decide[safe])
+    assert not gacc[~fin].any()
+    np.testing.assert_allclose(win.X.cpu().numpy().astype(np.float64), Xcur, rtol=0, atol=0)
+
+
+def test_param_moves_fp32_match_direct_sum(ctx):
+    prob = _problem(4096)
+    X = _perturbed(prob, 5).astype(np.float32).astype(np.float64)
+    p = prob.p_true * 1.02
+    I32 = prob.I.astype(np.float32).astype(np.float64)
+    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 5, "fp32", flags=P._lib.PIMC_PARAMS)
+    gpdA = gd.pdA.cpu().numpy()
+    gpprop = gd.pprop.cpu().numpy()
+    gacc = gd.paccept.cpu().numpy().astype(bool)
+    cur = p.copy()
+    for l in range(7):
+        pp = cur.copy()
+        pp[l] = gpprop[l]
+        ref = OA.delta_params(prob.model, X, I32, cur, pp)
+        assert gpdA[l] == pytest.approx(ref, rel=1e-9, abs=1e-9), l
+        if gacc[l]:
+            cur = pp
+    np.testing.assert_allclose(win.p.cpu().numpy(), cur, rtol=1e-15)
+
+
+def test_multi_sweep_fp64_chain_and_stats(ctx):
+    prob = _problem(300, init="guess", mask=W.configs.MASK_C1)
+    n = 40
+    X, p = prob.X0.copy(), prob.p0.copy()
+    st = OS.Stats(prob.M, 4, 7, n, burn=10, xref=prob.X0.copy())
+    OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=3, sweep0=100, n_sweeps=n,
+           w_state=prob.w_state, w_param=prob.w_param, stats=st)
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    gst = P.SweepStats.allocate(win, n, burn=10)
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=3, sweep0=100, w=w, n_sweeps=n, stats=gst)
+    assert ctx.sync() == 0
+    np.testing.assert_allclose(win.X.cpu().numpy(), X, rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(win.p.cpu().numpy(), p, rtol=1e-12)
+    np.testing.assert_allclose(gst.ptrace.cpu().numpy(), st.ptrace, rtol=1e-12)
+    np.testing.assert_allclose(gst.sum.cpu().numpy(), st.sum, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(gst.sumsq.cpu().numpy(), st.sumsq, rtol=1e-9, atol=1e-12)
+    np.testing.assert_array_equal(gst.acc.cpu().numpy(), st.acc)
+
+
+def test_tiling_invariance_fp32(ctx):
+    prob = _problem(1000)
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    outs = []
+    for K in (4, 8, 16):
+        ctx.set_tile(K)
+        win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+        P.pimc_sweep(ctx, prob.model, win, seed=9, chain=1, sweep0=0, w=w, n_sweeps=25)
+        assert ctx.sync() == 0
+        outs.append((win.X.cpu().numpy(), win.p.cpu().numpy()))
+    ctx.set_tile(0)
+    for X, p in outs[1:]:
+        np.testing.assert_array_equal(X, outs[0][0])
+        np.testing.assert_allclose(p, outs[0][1], rtol=1e-14)
+
+
+def test_batch_window_equals_single_run(ctx):
+    Ms = [37, 300, 64, 129]
+    probs = [W.make_hh_problem(M, 0.02, 200 + i, require_spike=False) for i, M in enumerate(Ms)]
+    spec = probs[0].model
+    chains = [5, 6, 7, 8]
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], chains, "fp32")
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+    P.pimc_run_batch(ctx, spec, batch, seed=4, sweep0=10, w=w, n_sweeps=15)
+    assert ctx.sync() == 0
+    for i, q in enumerate(probs):
+        win = P.Window.from_arrays(q.X0, q.p0, q.y, q.I, "fp32")
+        P.pimc_sweep(ctx, spec, win, seed=4, chain=chains[i], sweep0=10, w=w, n_sweeps=15)
+        assert ctx.sync() == 0
+        Xb, pb, _, _ = batch.window(i)
+        np.testing.assert_array_equal(Xb.cpu().numpy(), win.X.cpu().numpy())
+        np.testing.assert_allclose(pb.cpu().numpy(), win.p.cpu().numpy(), rtol=1e-14)
+
+
+def test_param_update_entry_point(ctx):
+    prob = _problem(256)
+    X = _perturbed(prob, 6)
+    p = prob.p_true.copy()
+    Xo, po, od, so = _oracle_one_sweep(prob, X, p, 42, flags=OS.PARAMS)
+    win = P.Window.from_arrays(X, p, prob.y, prob.I, "fp64")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    dbg = P.SweepDebug.allocate(win)
+    P.pimc_param_update(ctx, prob.model, win, seed=prob.seed, chain=0, sweep0=42, w=w, debug=dbg)
+    assert ctx.sync() == 0
+    np.testing.assert_array_equal(win.X.cpu().numpy(), X)
+    np.testing.assert_allclose(dbg.pdA.cpu().numpy(), od.pdA, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(win.p.cpu().numpy(), po, rtol=1e-14)
+
+
+def test_uniform_proposal_fp64(ctx):
+    prob = _problem(64, proposal="uniform")
+    X = _perturbed(prob, 7)
+    Xo, po, od, so = _oracle_one_sweep(prob, X, prob.p_true, 3)
+    win, gd, gs = _gpu_one_sweep(ctx, prob, X, prob.p_true, 3, "fp64")
+    np.testing.assert_allclose(gd.xprop.cpu().numpy(), od.xprop, rtol=1e-15, atol=1e-15)
+    _check_sites(gd, od, 1e-12, lambda d: 1e-6)
+
+
+def test_out_of_box_state_reported(ctx):
+    prob = _problem(40)
+    X = prob.X0.copy()
+    X[5, 1] = 1.5   # gate outside [0, 1]
+    win = P.Window.from_arrays(X, prob.p0, prob.y, prob.I, "fp64")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=3)
+    assert ctx.sync() == P._lib.PIMC_ERR_BOX
+    np.testing.assert_array_equal(win.X.cpu().numpy(), X)   # untouched
+    assert ctx.sync() == 0                                   # flag cleared
+
+
+def test_nonfinite_data_reported(ctx):
+    prob = _problem(40)
+    y = prob.y.copy()
+    y[7] = np.nan
+    win = P.Window.from_arrays(prob.X0, prob.p0, y, prob.I, "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    st = P.SweepStats.allocate(win, 2, moments=False)
+    P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=2, stats=st)
+    assert ctx.sync() == P._lib.PIMC_ERR_NONFINITE
+    assert st.acc.cpu().numpy()[9] >= 2

@@ -97,7 +97,9 @@ typedef struct {
  *               sum (x - xref) and sum (x - xref)^2
  *   xref        [M+1][4] in path precision (required when sum/sumsq given)
  *   ptrace      [n_sweeps][7] FP64: p after every sweep of the call (written)
- *   acc         [PIMC_NACC] int64 acceptance counters (+=) */
+ *   acc         [PIMC_NACC] int64 acceptance counters (+=)
+ *   stride      moments are accumulated at sweeps k >= burn with (k - burn) % stride == 0
+ *               (the N_skip of Section 4.1; values <= 1 mean every sweep) */
 typedef struct {
   double* sum;
   double* sumsq;
@@ -105,6 +107,7 @@ typedef struct {
   double* ptrace;
   int64_t* acc;
   int64_t burn;
+  int64_t stride;
 } pimc_stats;
 
 /* What the LAST sweep of a call proposed and decided (every pointer nullable).
@@ -138,7 +141,8 @@ typedef struct {
 
 /* Per-window statistics of a batch (every pointer nullable; device memory).
  *   sum, sumsq [S][4] FP64 packed like X; xref [S][4] path precision;
- *   ptrace [B][n_sweeps][7] FP64; acc [B][PIMC_NACC] int64. */
+ *   ptrace [B][n_sweeps][7] FP64; acc [B][PIMC_NACC] int64; burn, stride as
+ *   for pimc_stats. */
 typedef struct {
   double* sum;
   double* sumsq;
@@ -146,6 +150,7 @@ typedef struct {
   double* ptrace;
   int64_t* acc;
   int64_t burn;
+  int64_t stride;
 } pimc_batch_stats;
 
 /* Create a context bound to HIP device `device` (it owns only its workspace:

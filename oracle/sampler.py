@@ -43,8 +43,10 @@ N_ACC = 10
 
 @dataclass
 class Stats:
-    """Shifted moments sum(x - xref), sum((x - xref)^2) over sweeps k >= burn,
-    the parameter vector after every sweep, and acceptance counters."""
+    """Shifted moments sum(x - xref), sum((x - xref)^2) over the sweeps
+    k >= burn with (k - burn) % stride == 0 (statistics are taken only every
+    N_skip-th path update after the initial phase, Section 4.1), the
+    parameter vector after every sweep, and acceptance counters."""
 
     M: int
     D: int
@@ -52,6 +54,7 @@ class Stats:
     n_sweeps: int
     burn: int = 0
     xref: Optional[np.ndarray] = None
+    stride: int = 1
     sum: np.ndarray = field(init=False)
     sumsq: np.ndarray = field(init=False)
     ptrace: np.ndarray = field(init=False)
@@ -218,7 +221,7 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
             param_moves(spec, X, I, p, k, w_param, seed, chain, acc=acc, debug=dbg)
         if stats is not None:
             stats.ptrace[i] = p
-            if k >= stats.burn:
+            if k >= stats.burn and (k - stats.burn) % max(stats.stride, 1) == 0:
                 d = X - (stats.xref if stats.xref is not None else 0.0)
                 stats.sum += d
                 stats.sumsq += d * d

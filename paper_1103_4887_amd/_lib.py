@@ -45,7 +45,7 @@ class Rng(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("xref", C.c_void_p),
-                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64)]
+                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64)]
 
 
 class Debug(C.Structure):
@@ -61,7 +61,7 @@ class Batch(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("xref", C.c_void_p),
-                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64)]
+                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64)]
 
 
 _SIGS = {

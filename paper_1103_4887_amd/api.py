@@ -128,11 +128,13 @@ class SweepStats:
     ptrace: Optional[torch.Tensor] = None
     acc: Optional[torch.Tensor] = None
     burn: int = 0
+    stride: int = 1
 
     @staticmethod
-    def allocate(win: Window, n_sweeps: int, burn: int = 0, moments: bool = True, trace: bool = True):
+    def allocate(win: Window, n_sweeps: int, burn: int = 0, moments: bool = True, trace: bool = True,
+                 stride: int = 1):
         dev = win.X.device
-        st = SweepStats(burn=burn)
+        st = SweepStats(burn=burn, stride=stride)
         if moments:
             st.sum = torch.zeros((win.M + 1, 4), dtype=torch.float64, device=dev)
             st.sumsq = torch.zeros_like(st.sum)
@@ -147,6 +149,7 @@ class SweepStats:
         s.sum, s.sumsq, s.xref = _ptr(self.sum), _ptr(self.sumsq), _ptr(self.xref)
         s.ptrace, s.acc = _ptr(self.ptrace), _ptr(self.acc)
         s.burn = int(self.burn)
+        s.stride = int(self.stride)
         return s
 
 
@@ -281,6 +284,7 @@ def pimc_run_batch(ctx: Context, spec, batch: PackedBatch, *, seed: int, sweep0:
         bs = L.BatchStats()
         bs.sum, bs.sumsq, bs.xref = _ptr(stats.sum), _ptr(stats.sumsq), _ptr(stats.xref)
         bs.ptrace, bs.acc, bs.burn = _ptr(stats.ptrace), _ptr(stats.acc), int(stats.burn)
+        bs.stride = int(stats.stride)
         st = C.byref(bs)
     L.check(ctx.lib.pimc_run_batch(ctx.h, C.byref(m), C.byref(b), int(seed), int(sweep0), _ptr(w),
                                    int(n_sweeps), int(flags), st, _stream(stream)), "pimc_run_batch")

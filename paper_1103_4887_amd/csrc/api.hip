@@ -92,23 +92,40 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
   return PIMC_OK;
 }
 
-// Sites per thread: the smallest supported K whose thread count fits.
-int choose_K(const pimc_ctx* ctx, int64_t maxM, bool fp64, int& NT) {
+// Sites per thread K and threads NT of the sweep kernel for windows of up to
+// maxM steps: the smallest K that keeps the workgroup within 256 threads (one
+// wave per SIMD, no register spills), else the smallest K that fits at all;
+// the statistics staging chunk takes the LDS that is left.
+int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, int& NT, int& stage) {
   static const int cand32[] = {4, 8, 16};
   static const int cand64[] = {4, 8};
   const int* cand = fp64 ? cand64 : cand32;
   const int nc = fp64 ? 2 : 3;
-  for (int i = 0; i < nc; ++i) {
-    const int K = cand[i];
-    if (ctx->tile_K && ctx->tile_K != K) continue;
-    const int64_t need = (maxM + K - 1) / K;
-    const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
-    if (nt <= pimc::sweep_max_threads(fp64, K)) {
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < nc; ++i) {
+      const int K = cand[i];
+      if (ctx->tile_K && ctx->tile_K != K) continue;
+      const int64_t need = (maxM + K - 1) / K;
+      const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
+      const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
+      if (nt > lim) continue;
+      const size_t base = pimc::sweep_smem_bytes((int)nt, K, fp64, 0) + pimc::LDS_STATIC_RESERVE;
+      if (base >= pimc::LDS_BYTES) continue;
+      const size_t ts = fp64 ? 8 : 4;
+      const int64_t room = (int64_t)((pimc::LDS_BYTES - base) / (4 * ts));
+      const int64_t st = std::min<int64_t>(nt * K + 1, room);
+      if (st < 64) continue;
       NT = (int)nt;
+      stage = (int)st;
       return K;
     }
   }
   return 0;
+}
+
+void fill_consts(pimc::SweepArgs& a) {
+  a.cf.init(a.m);
+  a.cd.init(a.m);
 }
 
 void fill_debug(pimc::SweepArgs& a, const pimc_debug* d) {
@@ -242,9 +259,13 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   int r = model_args(model, a.m);
   if (r) return r;
   const bool fp64 = path->prec == PIMC_FP64;
-  int NT = 0;
-  const int K = choose_K(ctx, path->M, fp64, NT);
+  int NT = 0, stage = 0;
+  const int K = choose_shape(ctx, path->M, fp64, NT, stage);
   if (!K) return PIMC_ERR_UNSUPPORTED;
+  if (path->M >= (1ll << 30)) return PIMC_ERR_UNSUPPORTED;
+  fill_consts(a);
+  a.stage = stage;
+  a.stride = 1;
   a.offsets = nullptr;
   a.M_single = path->M;
   a.X = path->X;
@@ -264,6 +285,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.ptrace = stats->ptrace;
     a.acc = stats->acc;
     a.burn = stats->burn;
+    a.stride = stats->stride > 1 ? stats->stride : 1;
   }
   fill_debug(a, debug);
   a.err = ctx->err;
@@ -298,9 +320,12 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   int r = model_args(model, a.m);
   if (r) return r;
   const bool fp64 = b->prec == PIMC_FP64;
-  int NT = 0;
-  const int K = choose_K(ctx, maxM, fp64, NT);
+  int NT = 0, stage = 0;
+  const int K = choose_shape(ctx, maxM, fp64, NT, stage);
   if (!K) return PIMC_ERR_UNSUPPORTED;
+  fill_consts(a);
+  a.stage = stage;
+  a.stride = 1;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
   if ((r = ensure_batch(ctx, (size_t)B))) return r;
   // longest windows first, so the tail of the launch holds the short ones
@@ -333,6 +358,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     a.ptrace = stats->ptrace;
     a.acc = stats->acc;
     a.burn = stats->burn;
+    a.stride = stats->stride > 1 ? stats->stride : 1;
   }
   a.err = ctx->err;
   return pimc::launch_sweep(a, fp64, K, B, NT, s);

@@ -118,7 +118,7 @@ struct Consts {
   // current parameters (site precision)
   T p[7];
 
-  __device__ __forceinline__ void init(const ModelArgs& m) {
+  __host__ __device__ void init(const ModelArgs& m) {
     h = (T)(0.5 * m.dt);
     for (int a = 0; a < 4; ++a) {
       half_beta_Rd[a] = (T)(0.5 * m.beta * m.Rd[a]);
@@ -137,6 +137,15 @@ struct Consts {
     for (int l = 0; l < 7; ++l) p[l] = (T)pd[l];
   }
 };
+
+// Values that every lane of a wave holds identically (the parameters after
+// a move) are moved to scalar registers, which frees vector registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // dV/dt of Section 5.1: p1 I + p2 m^3 h (p3 - V) + p4 n^4 (p5 - V) + p6 (p7 - V)
 template <typename T>

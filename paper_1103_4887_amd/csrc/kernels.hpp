@@ -10,6 +10,8 @@ namespace pimc {
 
 struct SweepArgs {
   ModelArgs m;
+  Consts<float> cf;   // site constants, pre-converted on the host
+  Consts<double> cd;
   // windows: offsets == nullptr means one window of M_single + 1 sites
   const int64_t* offsets;
   const int32_t* order;  // block -> window map (nullable: identity)
@@ -32,6 +34,8 @@ struct SweepArgs {
   double* ptrace;
   int64_t* acc;
   int64_t burn;
+  int64_t stride;     // statistics every stride-th sweep from burn on
+  int32_t stage;      // sites per LDS staging chunk of the statistics pass
   // last-sweep debug record (nullable)
   void* dbg_xprop;
   double* dbg_dA;
@@ -42,7 +46,9 @@ struct SweepArgs {
   uint32_t* err;  // bit 0: non-finite dA met, bit 1: entry state outside box
 };
 
-size_t sweep_smem_bytes(int NT, bool fp64);
+size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage);
+constexpr size_t LDS_BYTES = 160 * 1024;       // LDS per CU on gfx950
+constexpr size_t LDS_STATIC_RESERVE = 1024;    // kept free for the kernels' static LDS
 int sweep_max_threads(bool fp64, int K);
 int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s);
 

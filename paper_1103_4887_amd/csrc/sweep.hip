@@ -37,6 +37,27 @@ struct Nb {  // a neighbour site: state and cached F
   T F[4];
 };
 
+// Sum over eight neighbouring lanes (xor 1, 2, 4).
+__device__ __forceinline__ double oct_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+// Accept iff log u < -dA, decided in FP64.  log u is first formed in FP32
+// (hardware log2); only when -dA lies within a margin far wider than that
+// estimate's error is the FP64 logarithm evaluated, so the decision is the
+// FP64 one at a fraction of its cost.
+__device__ __forceinline__ bool accept_u(uint32_t uword, double dA) {
+  const float lu32 = __builtin_amdgcn_logf(u01_f(uword)) * 0.6931471805599453f;
+  const double gap = -dA - (double)lu32;
+  const double E = 1e-5 * (1.0 + (double)__builtin_fabsf(lu32));
+  if (gap > E) return true;
+  if (gap < -E) return false;
+  return ::log(u01_d(uword)) < -dA;
+}
+
 // One Metropolis site update.  Returns true on accept (x, F replaced).
 template <typename T>
 __device__ __forceinline__ bool site_update(const Consts<T>& C, const T (&w)[4], bool uniform_prop,
@@ -89,9 +110,8 @@ __device__ __forceinline__ bool site_update(const Consts<T>& C, const T (&w)[4],
   T sobs = (T)0;
   if (hasObs) sobs = C.half_Ro * dx[0] * (dx[0] - (T)2 * (y - x[0]));
   double dA = (double)sdyn + (double)sobs;
-  const double lu = ::log(u01_d(uword));
   const bool fin = __builtin_isfinite(dA);
-  const bool acc = inbox && fin && (lu < -dA);
+  const bool acc = inbox && fin && accept_u(uword, dA);
   if (inbox && !fin) ++nonfinite;
   dA_out = inbox ? dA : __builtin_nan("");
   if (acc) {
@@ -187,43 +207,39 @@ template <> struct ThetaMove<6> { static constexpr int ia = 6, ib = -1; };
 __host__ __device__ constexpr int symi(int a, int b) { return a <= b ? sym7(a, b) : sym7(b, a); }
 
 // One Metropolis move of parameter L against the sufficient statistics.
+// z: proposal step, uword: Philox word of the accept uniform (drawn beforehand).
 template <int L>
-__device__ __forceinline__ void param_move(const SweepArgs& a, Key key, uint64_t k, bool uniform_prop,
-                                           const double (&wpar)[7], double (&pd)[7], double (&s)[7],
-                                           const double (&G)[28], bool& changed, int& acc, int& nonfin,
-                                           bool last, int win) {
+__device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_t uword, const double (&wpar)[7],
+                                           double (&pd)[7], double (&s)[7], const double (&G)[28], bool& changed,
+                                           int& acc, int& nonfin, bool rec, int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
-  const U4 b = draw(key, (uint32_t)L, k, TAG_PARAM);
-  double z, z1;
-  if (uniform_prop)
-    z = Math<double>::uniform_pm1(b.x);
-  else
-    Math<double>::box_muller(b.x, b.y, z, z1);
-  const double u = u01_d(b.z);
   const double pl = pd[L] + wpar[L] * z;
   double dA = __builtin_nan("");
   bool ok = false;
   if (pl >= a.m.p_lo[L] && pl <= a.m.p_hi[L]) {
-    constexpr int ia = ThetaMove<L>::ia, ib = ThetaMove<L>::ib;
+    constexpr int ia = ThetaMove<L>::ia;
+    constexpr int ib = ThetaMove<L>::ib;
+    constexpr int ibb = ib >= 0 ? ib : 0;
     const double dp = pl - pd[L];
-    // p2, p4, p6 move theta_l and theta_{l+1} = p_l p_{l+1}; p3, p5, p7 move p_{l-1} p_l
-    const double da = (L == 2 || L == 4 || L == 6) ? pd[L - 1 < 0 ? 0 : L - 1] * dp : dp;
-    const double db = ib >= 0 ? dp * pd[ib >= 0 ? ib : 0] : 0.0;
+    // p1, p2, p4, p6 move theta_L directly (and p2, p4, p6 also p_L p_{L+1});
+    // p3, p5, p7 move theta_L = p_{L-1} p_L
+    const double da = (L == 2 || L == 4 || L == 6) ? pd[L == 0 ? 0 : L - 1] * dp : dp;
+    const double db = ib >= 0 ? dp * pd[ibb] : 0.0;
     double quad = da * da * G[symi(ia, ia)];
     double lin = da * s[ia];
     if (ib >= 0) {
-      quad += 2.0 * da * db * G[symi(ia, ib >= 0 ? ib : 0)] + db * db * G[symi(ib >= 0 ? ib : 0, ib >= 0 ? ib : 0)];
-      lin += db * s[ib >= 0 ? ib : 0];
+      quad += 2.0 * da * db * G[symi(ia, ibb)] + db * db * G[symi(ibb, ibb)];
+      lin += db * s[ibb];
     }
     dA = 0.5 * a.m.beta * a.m.Rd[0] * (quad - 2.0 * lin);
     const bool fin = __builtin_isfinite(dA);
-    ok = fin && (::log(u) < -dA);
+    ok = fin && accept_u(uword, dA);
     if (!fin) ++nonfin;
     if (ok) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         double gs = G[symi(j, ia)] * da;
-        if (ib >= 0) gs += G[symi(j, ib >= 0 ? ib : 0)] * db;
+        if (ib >= 0) gs += G[symi(j, ibb)] * db;
         s[j] -= gs;
       }
       pd[L] = pl;
@@ -231,7 +247,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, Key key, uint64_t
       ++acc;
     }
   }
-  if (last) {
+  if (rec) {
     if (a.dbg_pprop) a.dbg_pprop[win * 7 + L] = pl;
     if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = dA;
     if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
@@ -261,15 +277,21 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   const Key key = make_key(a.seed, chain);
   double* P = a.p + (int64_t)win * 7;
 
-  T* lfirst = (T*)smem;          // [NT][8]
-  T* llast = lfirst + NT * 8;    // [NT][8]
-  double* lred = (double*)(llast + NT * 8);  // [16][NRED]
-  double* lstat = lred + 16 * NRED;          // [NRED]
-  double* lpar = lstat + NRED;               // [8]: p, changed flag
-  int* lcnt = (int*)(lpar + 8);              // [16] counters
+  // ---- LDS ----------------------------------------------------------------
+  T* lfirst = (T*)smem;                           // [NT][8] first site of each thread
+  T* llast = lfirst + NT * 8;                     // [NT][8] last site of each thread
+  T* lyi = llast + NT * 8;                        // [NT*K+1][2] (y_n, I_n) of the window
+  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [NRED][8*NW] partials of 8 lanes
+  double* lstat = lred + NRED * 8 * NW;           // [NRED]
+  double* ldraw = lstat + NRED;                   // [16]: z_l, log u_l of the parameter moves
+  int* lcnt = (int*)(ldraw + 16);                 // [16]
+  T* lstage = (T*)(lcnt + 16);                    // [stage][4] statistics staging
 
   Consts<T> C;
-  C.init(a.m);
+  if constexpr (sizeof(T) == 4)
+    C = a.cf;
+  else
+    C = a.cd;
   double pd[7];
 #pragma unroll
   for (int l = 0; l < 7; ++l) pd[l] = P[l];
@@ -283,28 +305,34 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   const bool uniform_prop = a.m.proposal == PIMC_PROP_UNIFORM;
   const double hD = 0.5 * a.m.dt;
 
+  // observations and drive of the whole window -> LDS
+  {
+    const T* Yw = (const T*)a.y + base;
+    const T* Iw = (const T*)a.I + base;
+    for (int n = t; n <= M; n += NT) {
+      lyi[2 * n] = Yw[n];
+      lyi[2 * n + 1] = Iw[n];
+    }
+  }
+
   // ---- own sites: n = n0 + j, j < K, plus site M on the last thread when
   //      the regular slots stop exactly at M ------------------------------
   const int NTneed = (M + K - 1) / K;
   const bool active = t < NTneed;
   const int n0 = t * K;
   const bool has_extra = (t == NTneed - 1) && (K * NTneed == M);
-  // per-thread base pointers: every slot access below is a constant offset
   T* Xt = (T*)a.X + (base + n0) * 4;
-  const T* Yt = (const T*)a.y + base + n0;
-  const T* It = (const T*)a.I + base + n0;
+  __syncthreads();
 
-  T x[K][4], F[K][4], yv[K], Iv[K];
-  T xe[4], Fe[4], ye = 0, Ie = 0;
+  T x[K][4], F[K][4];
+  T xe[4], Fe[4];
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const bool v = active && n0 + j <= M;
 #pragma unroll
     for (int c = 0; c < 4; ++c) x[j][c] = v ? Xt[j * 4 + c] : C.lo[c];
-    yv[j] = v ? Yt[j] : (T)0;
-    Iv[j] = v ? It[j] : (T)0;
-    hh_F(C, x[j], Iv[j], F[j]);
+    hh_F(C, x[j], v ? lyi[2 * (n0 + j) + 1] : (T)0, F[j]);
     if (v) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) bad = bad || !(x[j][c] >= C.lo[c] && x[j][c] <= C.hi[c]);
@@ -312,13 +340,11 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) xe[c] = has_extra ? Xt[K * 4 + c] : C.lo[c];
+  hh_F(C, xe, has_extra ? lyi[2 * M + 1] : (T)0, Fe);
   if (has_extra) {
-    ye = Yt[K];
-    Ie = It[K];
 #pragma unroll
     for (int c = 0; c < 4; ++c) bad = bad || !(xe[c] >= C.lo[c] && xe[c] <= C.hi[c]);
   }
-  hh_F(C, xe, Ie, Fe);
   if (t == 0) {
 #pragma unroll
     for (int l = 0; l < 7; ++l) {
@@ -364,7 +390,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             Nb<T> L, R;
             const bool hasL = nn >= 1;
             if (j == 0) {
-              if (hasL) lds_get(C, llast + (t - 1) * 8, It[-1], L);
+              if (hasL) lds_get(C, llast + (t - 1) * 8, lyi[2 * nn - 1], L);
             } else {
 #pragma unroll
               for (int c = 0; c < 4; ++c) {
@@ -381,8 +407,8 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
             double dA;
             T xp[4];
-            const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], yv[j], Iv[j], hasL, L, hasR, R,
-                                        nn >= 1, blk, jj == 0 ? ub.x : ub.z, dA, xp, nonfin);
+            const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyi[2 * nn], lyi[2 * nn + 1], hasL, L,
+                                        hasR, R, nn >= 1, blk, jj == 0 ? ub.x : ub.z, dA, xp, nonfin);
             accE += ok;
             if (DBG && last) {
               if (dx_t)
@@ -407,8 +433,8 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         const U4 ub = draw(key, opaque((uint32_t)(M >> 2)), k, TAG_SACC);
         double dA;
         T xp[4];
-        const bool ok = site_update(C, ws, uniform_prop, xe, Fe, ye, Ie, true, L, false, R, true, blk, ub.x,
-                                    dA, xp, nonfin);
+        const bool ok = site_update(C, ws, uniform_prop, xe, Fe, lyi[2 * M], lyi[2 * M + 1], true, L, false, R,
+                                    true, blk, ub.x, dA, xp, nonfin);
         accE += ok;
         if (DBG && last) {
           if (dx_t)
@@ -442,7 +468,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
                   R.F[c] = Fe[c];
                 }
               } else {
-                lds_get(C, lfirst + (t + 1) * 8, It[K], R);
+                lds_get(C, lfirst + (t + 1) * 8, lyi[2 * nn + 3], R);
               }
             }
           } else {
@@ -455,8 +481,8 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
           double dA;
           T xp[4];
-          const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], yv[j], Iv[j], true, L, hasR, R, true, blk,
-                                      uodd[j >> 1], dA, xp, nonfin);
+          const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyi[2 * nn], lyi[2 * nn + 1], true, L,
+                                      hasR, R, true, blk, uodd[j >> 1], dA, xp, nonfin);
           accO += ok;
           if (DBG && last) {
             if (dx_t)
@@ -471,6 +497,27 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     }
 
     if (a.flags & PIMC_PARAMS) {
+      // ---- random numbers of the parameter moves (path independent), spread
+      //      over the waves: wave w, lane i draws for parameter w + i NW ------
+      {
+        const int l = wv + lane * NW;
+        if (lane * NW < 7 && l < 7) {
+          const U4 b = draw(key, opaque((uint32_t)l), k, TAG_PARAM);
+          double z;
+          if (uniform_prop) {
+            z = Math<double>::uniform_pm1(b.x);
+          } else if constexpr (sizeof(T) == 4) {
+            float z0, z1;
+            Math<float>::box_muller(b.x, b.y, z0, z1);
+            z = (double)z0;
+          } else {
+            double z1;
+            Math<double>::box_muller(b.x, b.y, z, z1);
+          }
+          ldraw[l] = z;
+          ldraw[8 + l] = __builtin_bit_cast(double, (uint64_t)b.z);
+        }
+      }
       // ---- sufficient statistics over the links of the odd sites ----------
       double th[7];
       theta_of(pd, th);
@@ -478,26 +525,26 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #pragma unroll
       for (int i = 0; i < NRED; ++i) st[i] = 0.0;
       if (active) {
-        Feat fl = feat_of(x[0], Iv[0]);
+        Feat fl = feat_of(x[0], lyi[2 * n0 + 1]);
 #pragma unroll
         for (int j = 1; j < K; j += 2) {
           const int nn = n0 + j;
           if (nn <= M) {
-            const Feat fc = feat_of(x[j], Iv[j]);
+            const Feat fc = feat_of(x[j], lyi[2 * nn + 1]);
             link_stats(th, hD, fl, fc, st);
             if (nn + 1 <= M) {
               Feat fr;
               if (j == K - 1) {
                 if (has_extra) {
-                  fr = feat_of(xe, Ie);
+                  fr = feat_of(xe, lyi[2 * M + 1]);
                 } else {
                   T xr[4];
 #pragma unroll
                   for (int c = 0; c < 4; ++c) xr[c] = lfirst[(t + 1) * 8 + c];
-                  fr = feat_of(xr, It[K]);
+                  fr = feat_of(xr, lyi[2 * nn + 3]);
                 }
               } else {
-                fr = feat_of(x[j + 1], Iv[j + 1]);
+                fr = feat_of(x[j + 1], lyi[2 * nn + 3]);
               }
               link_stats(th, hD, fc, fr, st);
               fl = fr;
@@ -505,52 +552,57 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           }
         }
       }
-      // ---- block reduction (fixed order for a given launch shape) ---------
+      // ---- block reduction: groups of 8 lanes in registers, then a
+      //      fixed-order sum of the group partials through LDS -------------
 #pragma unroll
-      for (int i = 0; i < NRED; ++i) {
-        double v = st[i];
+      for (int i = 0; i < NRED; ++i) st[i] = oct_sum(st[i]);
+      if ((lane & 7) == 0) {
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-        st[i] = v;
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NRED; ++i) lred[wv * NRED + i] = st[i];
+        for (int i = 0; i < NRED; ++i) lred[i * 8 * NW + wv * 8 + (lane >> 3)] = st[i];
       }
       __syncthreads();
       if (t < NRED) {
-        double s = 0.0;
-        for (int q = 0; q < NW; ++q) s += lred[q * NRED + t];
-        lstat[t] = s;
+        const double* row = lred + t * 8 * NW;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int q = 0; q < 8 * NW; q += 4) {
+          s0 += row[q];
+          s1 += row[q + 1];
+          s2 += row[q + 2];
+          s3 += row[q + 3];
+        }
+        lstat[t] = (s0 + s1) + (s2 + s3);
       }
       __syncthreads();
-      // ---- sequential parameter moves (one lane) --------------------------
-      if (t == 0) {
-        double s7[7], G[28];
+      // ---- sequential parameter moves, evaluated identically by every
+      //      wave (no broadcast and no further barrier needed) ---------------
+      {
+        double s7[7], G[28], zz[7];
+        uint32_t uw[7];
 #pragma unroll
-        for (int l = 0; l < 7; ++l) s7[l] = lstat[l];
+        for (int l = 0; l < 7; ++l) {
+          s7[l] = lstat[l];
+          zz[l] = ldraw[l];
+          uw[l] = (uint32_t)__builtin_bit_cast(uint64_t, ldraw[8 + l]);
+        }
 #pragma unroll
         for (int i = 0; i < 28; ++i) G[i] = lstat[7 + i];
         bool changed = false;
-        param_move<0>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[0], nonfin, last, win);
-        param_move<1>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[1], nonfin, last, win);
-        param_move<2>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[2], nonfin, last, win);
-        param_move<3>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[3], nonfin, last, win);
-        param_move<4>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[4], nonfin, last, win);
-        param_move<5>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[5], nonfin, last, win);
-        param_move<6>(a, key, k, uniform_prop, wpar, pd, s7, G, changed, accP[6], nonfin, last, win);
+        const bool rec = last && t == 0;
+        param_move<0>(a, zz[0], uw[0], wpar, pd, s7, G, changed, accP[0], nonfin, rec, win);
+        param_move<1>(a, zz[1], uw[1], wpar, pd, s7, G, changed, accP[1], nonfin, rec, win);
+        param_move<2>(a, zz[2], uw[2], wpar, pd, s7, G, changed, accP[2], nonfin, rec, win);
+        param_move<3>(a, zz[3], uw[3], wpar, pd, s7, G, changed, accP[3], nonfin, rec, win);
+        param_move<4>(a, zz[4], uw[4], wpar, pd, s7, G, changed, accP[4], nonfin, rec, win);
+        param_move<5>(a, zz[5], uw[5], wpar, pd, s7, G, changed, accP[5], nonfin, rec, win);
+        param_move<6>(a, zz[6], uw[6], wpar, pd, s7, G, changed, accP[6], nonfin, rec, win);
+        if (changed) {
 #pragma unroll
-        for (int l = 0; l < 7; ++l) lpar[l] = pd[l];
-        lpar[7] = changed ? 1.0 : 0.0;
-      }
-      __syncthreads();
-      if (lpar[7] != 0.0) {
+          for (int l = 0; l < 7; ++l) pd[l] = wave_uniform(pd[l]);
+          C.set_p(pd);
 #pragma unroll
-        for (int l = 0; l < 7; ++l) pd[l] = lpar[l];
-        C.set_p(pd);
-#pragma unroll
-        for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], Iv[j]);
-        Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], Ie);
+          for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], lyi[2 * (n0 + j) + 1]);
+          Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], has_extra ? lyi[2 * M + 1] : (T)0);
+        }
       }
     } else {
       __syncthreads();
@@ -561,28 +613,53 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #pragma unroll
       for (int l = 0; l < 7; ++l) a.ptrace[(int64_t)win * a.n_sweeps * 7 + it * 7 + l] = pd[l];
     }
-    if (a.sum && (int64_t)k >= a.burn && active) {
-      const T* xr = (const T*)a.xref + (base + n0) * 4;
-      double* su = a.sum + (base + n0) * 4;
-      double* sq = a.sumsq ? a.sumsq + (base + n0) * 4 : nullptr;
+    if (a.sum && (int64_t)k >= a.burn && ((int64_t)k - a.burn) % a.stride == 0) {
+      // stage the path through LDS so that the FP64 read-modify-write of the
+      // moment sums is coalesced (consecutive lanes, consecutive addresses)
+      const T* xr = (const T*)a.xref + base * 4;
+      double* su = a.sum + base * 4;
+      double* sq = a.sumsq ? a.sumsq + base * 4 : nullptr;
+      const int S = a.stage;
+      for (int c0 = 0; c0 <= M; c0 += S) {
+        if (active) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        if (n0 + j <= M) {
+          for (int j = 0; j < K; ++j) {
+            const int n = n0 + j;
+            if (n <= M && n >= c0 && n < c0 + S) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const double d = (double)x[j][c] - (double)xr[j * 4 + c];
-            su[j * 4 + c] += d;
-            if (sq) sq[j * 4 + c] += d * d;
+              for (int c = 0; c < 4; ++c) lstage[(n - c0) * 4 + c] = x[j][c];
+            }
+          }
+          if (has_extra && M >= c0 && M < c0 + S) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) lstage[(M - c0) * 4 + c] = xe[c];
           }
         }
-      }
-      if (has_extra) {
+        __syncthreads();
+        const int cnt = 4 * min(S, M + 1 - c0);
+        // eight independent elements per round: all loads are in flight
+        // before the first add, so the loop is bandwidth- not latency-bound
+        for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
+          double dv[8], s1[8], s2[8];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double d = (double)xe[c] - (double)xr[K * 4 + c];
-          su[K * 4 + c] += d;
-          if (sq) sq[K * 4 + c] += d * d;
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            const int64_t g = (int64_t)c0 * 4 + e;
+            dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
+            s1[u] = e < cnt ? su[g] : 0.0;
+            s2[u] = (e < cnt && sq) ? sq[g] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            const int64_t g = (int64_t)c0 * 4 + e;
+            if (e < cnt) {
+              su[g] = s1[u] + dv[u];
+              if (sq) sq[g] = s2[u] + dv[u] * dv[u];
+            }
+          }
         }
+        __syncthreads();
       }
     }
   }
@@ -604,14 +681,18 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     for (int l = 0; l < 7; ++l) P[l] = pd[l];
   }
   // ---- acceptance counters ----------------------------------------------
+  __syncthreads();
   if (t < 16) lcnt[t] = 0;
   __syncthreads();
   if (accE) atomicAdd(&lcnt[0], accE);
   if (accO) atomicAdd(&lcnt[1], accO);
-  if (nonfin) atomicAdd(&lcnt[9], nonfin);
+  if (nonfin && lane != 0) atomicAdd(&lcnt[9], nonfin);
   if (t == 0) {
+    // parameter counts (and their non-finite count) are identical in every
+    // wave; lane 0 of wave 0 reports them once
 #pragma unroll
     for (int l = 0; l < 7; ++l) lcnt[2 + l] += accP[l];
+    if (nonfin) atomicAdd(&lcnt[9], nonfin);
   }
   __syncthreads();
   if (t == 0) {
@@ -623,37 +704,65 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   }
 }
 
-size_t sweep_smem_bytes(int NT, bool fp64) {
+size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
   const size_t ts = fp64 ? 8 : 4;
-  return (size_t)NT * 8 * ts * 2 + (16 * NRED + NRED + 8) * sizeof(double) + 16 * sizeof(int);
+  const size_t NW = (size_t)NT / 64;
+  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 8 * NW + NRED + 16) * sizeof(double) +
+         16 * sizeof(int) + (size_t)stage * 4 * ts;
 }
 
-#define PIMC_SWEEP_LAUNCH(T, K, MAXT)                                                          \
-  do {                                                                                         \
-    if (dbg)                                                                                   \
-      hipLaunchKernelGGL((sweep_kernel<T, K, MAXT, true>), dim3(nblocks), dim3(NT), sm, s, a);  \
-    else                                                                                       \
-      hipLaunchKernelGGL((sweep_kernel<T, K, MAXT, false>), dim3(nblocks), dim3(NT), sm, s, a); \
+// The launch is refused on the host (never enqueued) when the kernel's static
+// LDS plus the requested dynamic LDS exceeds what a workgroup may allocate.
+template <typename Kern>
+static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s, const SweepArgs& a) {
+  hipFuncAttributes at;
+  if (hipFuncGetAttributes(&at, (const void*)k) != hipSuccess) return PIMC_ERR_HIP;
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PIMC_ERR_HIP;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
+  if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), sm, s, a);
+  return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
+}
+
+#define PIMC_SWEEP_LAUNCH(T, K, MAXT)                                                \
+  do {                                                                               \
+    if (dbg)                                                                         \
+      return launch_checked(sweep_kernel<T, K, MAXT, true>, nblocks, NT, sm, s, a);  \
+    else                                                                             \
+      return launch_checked(sweep_kernel<T, K, MAXT, false>, nblocks, NT, sm, s, a); \
+  } while (0)
+
+// Launch bounds follow the thread count: up to 256 threads (one wave per
+// SIMD) a wave may hold 512 registers (architectural + accumulation), so the
+// register-resident path never spills to scratch.
+#define PIMC_SWEEP_PICK(T, K, BIG)          \
+  do {                                      \
+    if (NT <= 256)                          \
+      PIMC_SWEEP_LAUNCH(T, K, 256);         \
+    else                                    \
+      PIMC_SWEEP_LAUNCH(T, K, BIG);         \
   } while (0)
 
 int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s) {
-  const size_t sm = sweep_smem_bytes(NT, fp64);
+  const size_t sm = sweep_smem_bytes(NT, K, fp64, a.stage);
+  if (sm + LDS_STATIC_RESERVE > LDS_BYTES || NT > sweep_max_threads(fp64, K)) return PIMC_ERR_UNSUPPORTED;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   if (fp64) {
     switch (K) {
-      case 4: PIMC_SWEEP_LAUNCH(double, 4, 1024); break;
-      case 8: PIMC_SWEEP_LAUNCH(double, 8, 512); break;
+      case 4: PIMC_SWEEP_PICK(double, 4, 1024); break;
+      case 8: PIMC_SWEEP_PICK(double, 8, 512); break;
       default: return PIMC_ERR_UNSUPPORTED;
     }
   } else {
     switch (K) {
-      case 4: PIMC_SWEEP_LAUNCH(float, 4, 1024); break;
-      case 8: PIMC_SWEEP_LAUNCH(float, 8, 512); break;
-      case 16: PIMC_SWEEP_LAUNCH(float, 16, 512); break;
+      case 4: PIMC_SWEEP_PICK(float, 4, 1024); break;
+      case 8: PIMC_SWEEP_PICK(float, 8, 512); break;
+      case 16: PIMC_SWEEP_PICK(float, 16, 512); break;
       default: return PIMC_ERR_UNSUPPORTED;
     }
   }
-  return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
+  return PIMC_ERR_UNSUPPORTED;
 }
 
 int sweep_max_threads(bool fp64, int K) {

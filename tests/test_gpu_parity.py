@@ -210,11 +210,11 @@ def test_multi_sweep_fp64_chain_and_stats(ctx):
     prob = _problem(300, init="guess", mask=W.configs.MASK_C1)
     n = 40
     X, p = prob.X0.copy(), prob.p0.copy()
-    st = OS.Stats(prob.M, 4, 7, n, burn=10, xref=prob.X0.copy())
+    st = OS.Stats(prob.M, 4, 7, n, burn=110, xref=prob.X0.copy(), stride=4)
     OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=3, sweep0=100, n_sweeps=n,
            w_state=prob.w_state, w_param=prob.w_param, stats=st)
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
-    gst = P.SweepStats.allocate(win, n, burn=10)
+    gst = P.SweepStats.allocate(win, n, burn=110, stride=4)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=3, sweep0=100, w=w, n_sweeps=n, stats=gst)
     assert ctx.sync() == 0
@@ -224,6 +224,28 @@ def test_multi_sweep_fp64_chain_and_stats(ctx):
     np.testing.assert_allclose(gst.sum.cpu().numpy(), st.sum, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(gst.sumsq.cpu().numpy(), st.sumsq, rtol=1e-9, atol=1e-12)
     np.testing.assert_array_equal(gst.acc.cpu().numpy(), st.acc)
+
+
+@pytest.mark.parametrize("M,stride", [(8192, 1), (4096, 3), (37, 2)])
+def test_moments_fp32_large_window(ctx, M, stride):
+    """Moment sums (staged through LDS in chunks at large M) equal the sums
+    of the chain's own states, sweep by sweep."""
+    prob = _problem(M)
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    st = P.SweepStats.allocate(win, 1, burn=2, stride=stride)
+    xref = st.xref.cpu().numpy().astype(np.float64)
+    S = np.zeros((M + 1, 4))
+    Q = np.zeros((M + 1, 4))
+    for k in range(9):
+        P.pimc_sweep(ctx, prob.model, win, seed=3, chain=0, sweep0=k, w=w, n_sweeps=1, stats=st)
+        if k >= 2 and (k - 2) % stride == 0:
+            d = win.X.cpu().numpy().astype(np.float64) - xref
+            S += d
+            Q += d * d
+    assert ctx.sync() == 0
+    np.testing.assert_allclose(st.sum.cpu().numpy(), S, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(st.sumsq.cpu().numpy(), Q, rtol=1e-12, atol=1e-15)
 
 
 def test_tiling_invariance_fp32(ctx):
@@ -307,3 +329,18 @@ def test_nonfinite_data_reported(ctx):
     P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=2, stats=st)
     assert ctx.sync() == P._lib.PIMC_ERR_NONFINITE
     assert st.acc.cpu().numpy()[9] >= 2
+
+
+def test_oversized_window_refused_on_host(ctx):
+    """A window whose LDS footprint exceeds the CU's LDS is refused before
+    anything is enqueued, and the context stays usable."""
+    prob = _problem(16384, init="truth")
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    with pytest.raises(P._lib.PimcError) as e:
+        P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
+    assert ctx.sync() == 0
+    small = P.Window.from_arrays(prob.X0[:65], prob.p0, prob.y[:65], prob.I[:65], "fp64")
+    P.pimc_sweep(ctx, prob.model, small, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    assert ctx.sync() == 0

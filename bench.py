@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="sites per thread (0: autotune)")
+    ap.add_argument("--tiles", type=int, default=-1, help="time tiles per window (-1: autotune)")
+    ap.add_argument("--nskip", type=int, default=10, help="path moments every nskip-th sweep (N_skip)")
     return ap.parse_args()
 
 
@@ -77,7 +79,7 @@ def main():
     import torch
 
     import paper_1103_4887_amd as P
-    from paper_1103_4887_amd import diag
+    from paper_1103_4887_amd import autotune, diag
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -85,18 +87,22 @@ def main():
     prob = W.config_problem(args.config)
     prec = cfg["prec"]
     ctx = P.Context(0)
-    if args.tile:
-        ctx.set_tile(args.tile)
     spec = prob.model
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, prec)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     K, Wm = args.steps, args.warmup
     stream = torch.cuda.current_stream()
+    if args.tiles < 0 and not args.tile:
+        shape = autotune.tune(ctx, spec, win, w)
+    else:
+        ctx.set_tile(args.tile)
+        ctx.set_tiles(max(args.tiles, 0))
+        shape = (args.tile, max(args.tiles, 0), None)
 
     # warm-up (also compiles nothing: the library is prebuilt)
     P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=0, sweep0=0, w=w, n_sweeps=max(Wm, 1))
     assert ctx.sync() == 0
-    stats = P.SweepStats.allocate(win, K, burn=Wm + K // 2)
+    stats = P.SweepStats.allocate(win, K, burn=Wm + K // 2, stride=args.nskip)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -125,7 +131,8 @@ def main():
         "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: HH window M={prob.M}, dt={spec.dt} ms, {prec} sites + f64 "
                                f"reductions, params mask 0x{spec.p_mask:x}, 1 chain, {K} sweeps",
-                   "M": prob.M, "sweeps": K, "chains": 1},
+                   "M": prob.M, "sweeps": K, "chains": 1, "nskip": args.nskip,
+                   "launch": {"K": shape[0], "tiles": shape[1]}},
         "param_ess_per_s": float(ess.min() / gpu_s),
         "param_ess_per_s_median": float(np.median(ess) / gpu_s),
         "param_ess": [float(v) for v in ess],
@@ -133,7 +140,8 @@ def main():
                         "params": [float(acc[2 + l] / K) for l in mask]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
-                     "frac_of_occupied_cus": achieved / (PEAK_SLOTS_PER_S / 256),
+                     "cus_occupied": max(1, shape[1]),
+                     "frac_of_occupied_cus": achieved / (PEAK_SLOTS_PER_S / 256 * max(1, shape[1])),
                      "kernel": "sweep_kernel", "slots_per_site_update": SLOTS_PER_SITE_UPDATE,
                      "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3},
     }

@@ -50,7 +50,8 @@ typedef enum {
   PIMC_ERR_NONFINITE = -3,    /* a non-finite action change was met (reported by pimc_sync) */
   PIMC_ERR_UNSUPPORTED = -4,  /* shape not supported by the built kernels */
   PIMC_ERR_NOMEM = -5,        /* workspace allocation failed */
-  PIMC_ERR_BOX = -6           /* state or parameter outside its box at entry (reported by pimc_sync) */
+  PIMC_ERR_BOX = -6,          /* state or parameter outside its box at entry (reported by pimc_sync) */
+  PIMC_ERR_TIMEOUT = -7       /* a wait between the time tiles of a window gave up (reported by pimc_sync) */
 } pimc_status;
 
 enum { PIMC_FP64 = 0, PIMC_FP32 = 1 };          /* site arithmetic precision */
@@ -163,8 +164,18 @@ void pimc_ctx_destroy(pimc_ctx* ctx);
  * numbers are addressed by (site, sweep), never by thread. */
 int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
 
+/* Time tiles per window for pimc_sweep: T >= 2 cuts the window into T
+ * workgroups of S sites each, (T-1) S < M <= T S, that exchange their
+ * boundary sites and all-reduce the parameter statistics through global
+ * memory (launched cooperatively so that all tiles are resident; every
+ * wait is bounded).  0 restores the automatic choice (one workgroup when the
+ * window fits, the fewest tiles otherwise); at most 256.  Only FP32 windows
+ * are tiled: an FP64 window that does not fit one workgroup is refused with
+ * PIMC_ERR_UNSUPPORTED.  pimc_run_batch always uses one workgroup per window. */
+int pimc_set_sweep_tiles(pimc_ctx* ctx, int T);
+
 /* Wait for `stream`, then return and clear any deferred device-side error
- * (PIMC_ERR_BOX first, then PIMC_ERR_NONFINITE). */
+ * (PIMC_ERR_TIMEOUT first, then PIMC_ERR_BOX, then PIMC_ERR_NONFINITE). */
 int pimc_sync(pimc_ctx* ctx, void* stream);
 
 const char* pimc_strerror(int status);

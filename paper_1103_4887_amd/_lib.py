@@ -17,6 +17,7 @@ PIMC_ERR_NONFINITE = -3
 PIMC_ERR_UNSUPPORTED = -4
 PIMC_ERR_NOMEM = -5
 PIMC_ERR_BOX = -6
+PIMC_ERR_TIMEOUT = -7
 PIMC_FP64 = 0
 PIMC_FP32 = 1
 PIMC_PROP_GAUSS = 0
@@ -68,6 +69,7 @@ _SIGS = {
     "pimc_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "pimc_ctx_destroy": (None, [C.c_void_p]),
     "pimc_set_sweep_tile": (C.c_int, [C.c_void_p, C.c_int]),
+    "pimc_set_sweep_tiles": (C.c_int, [C.c_void_p, C.c_int]),
     "pimc_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pimc_strerror": (C.c_char_p, [C.c_int]),
     "pimc_action": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p]),

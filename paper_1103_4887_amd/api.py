@@ -81,6 +81,9 @@ class Context:
     def set_tile(self, K: int):
         L.check(self.lib.pimc_set_sweep_tile(self.h, int(K)), "pimc_set_sweep_tile")
 
+    def set_tiles(self, T: int):
+        L.check(self.lib.pimc_set_sweep_tiles(self.h, int(T)), "pimc_set_sweep_tiles")
+
     def sync(self, stream=None) -> int:
         """Wait for the stream; returns the deferred device status (0 = ok)."""
         return int(self.lib.pimc_sync(self.h, _stream(stream)))

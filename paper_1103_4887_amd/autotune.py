@@ -1,0 +1,74 @@
+"""Launch-shape autotuner for the sweep kernel.
+
+The sweep's result does not depend on its launch shape (random numbers are
+addressed by site and sweep; the shape only changes the rounding order of the
+parameter statistics), so the shape is a pure performance choice: sites per
+thread K and time tiles T per window.  The tuner times a short run of every
+candidate on a scratch copy of the window and keeps the fastest; results are
+cached per (M, precision, parameter flags) for the process.
+"""
+
+from __future__ import annotations
+
+from typing import Dict, Iterable, Optional, Tuple
+
+import torch
+
+from . import _lib as L
+from .api import Context, Window, pimc_sweep
+
+_CACHE: Dict[Tuple[int, str, int], Tuple[int, int, float]] = {}
+
+
+def candidates(M: int, prec: str) -> Iterable[Tuple[int, int]]:
+    """(K, T) pairs worth timing; K = 0 / T = 0 mean the library's own choice."""
+    yield (0, 0)
+    if prec == "fp64":
+        for K in (4, 8):
+            yield (K, 1)
+        return
+    for K in (4, 8, 16):
+        yield (K, 1)
+    for T in (2, 4, 8, 16, 32, 64, 128):
+        if M // T >= 256:
+            yield (0, T)
+
+
+def tune(ctx: Context, spec, win: Window, w: torch.Tensor, *, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
+         sweeps: int = 200, seed: int = 12345, verbose: bool = False) -> Tuple[int, int, float]:
+    """Pick (K, T) for this window; applies it to ctx and returns (K, T, us_per_sweep)."""
+    key = (win.M, win.prec, flags)
+    if key in _CACHE:
+        K, T, us = _CACHE[key]
+        ctx.set_tile(K)
+        ctx.set_tiles(T)
+        return K, T, us
+    best: Optional[Tuple[int, int, float]] = None
+    scratch = Window(X=win.X.clone(), p=win.p.clone(), y=win.y, I=win.I, prec=win.prec)
+    for K, T in candidates(win.M, win.prec):
+        ctx.set_tile(K)
+        ctx.set_tiles(T)
+        try:
+            pimc_sweep(ctx, spec, scratch, seed=seed, chain=0, sweep0=0, w=w, n_sweeps=10, flags=flags)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pimc_sweep(ctx, spec, scratch, seed=seed, chain=0, sweep0=10, w=w, n_sweeps=sweeps, flags=flags)
+            e1.record()
+            torch.cuda.synchronize()
+        except L.PimcError:
+            continue
+        if ctx.sync() != 0:
+            continue
+        us = e0.elapsed_time(e1) * 1e3 / sweeps
+        if verbose:
+            print(f"autotune M={win.M} {win.prec} K={K} T={T}: {us:.2f} us/sweep", flush=True)
+        if best is None or us < best[2]:
+            best = (K, T, us)
+    if best is None:
+        raise RuntimeError("no launch shape of the sweep kernel runs this window")
+    _CACHE[key] = best
+    ctx.set_tile(best[0])
+    ctx.set_tiles(best[1])
+    return best

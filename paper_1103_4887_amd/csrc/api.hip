@@ -20,7 +20,18 @@ struct pimc_ctx {
   int32_t* order = nullptr;       // batch launch order (device)
   size_t batch_cap = 0;           // in windows
   int tile_K = 0;                 // 0 = automatic choice of sites per thread
+  int tiles = 0;                  // 0 = automatic number of time tiles per window
+  // cross-tile workspace of one window split over up to MAX_TILES workgroups
+  void* halo = nullptr;
+  uint32_t* hflag = nullptr;
+  double* wpart = nullptr;
+  uint32_t* wsync = nullptr;
+  uint64_t spin_ticks = 0;
 };
+
+namespace {
+constexpr int MAX_TILES = 256;
+}
 
 namespace {
 
@@ -92,33 +103,66 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
   return PIMC_OK;
 }
 
-// Sites per thread K and threads NT of the sweep kernel for windows of up to
-// maxM steps: the smallest K that keeps the workgroup within 256 threads (one
-// wave per SIMD, no register spills), else the smallest K that fits at all;
-// the statistics staging chunk takes the LDS that is left.
-int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, int& NT, int& stage) {
+// Statistics staging chunk: the LDS left after the kernel's other buffers.
+int64_t stage_room(int NT, int K, bool fp64) {
+  const size_t base = pimc::sweep_smem_bytes(NT, K, fp64, 0) + pimc::LDS_STATIC_RESERVE;
+  if (base >= pimc::LDS_BYTES) return 0;
+  const size_t ts = fp64 ? 8 : 4;
+  return std::min<int64_t>((int64_t)NT * K + 1, (int64_t)((pimc::LDS_BYTES - base) / (4 * ts)));
+}
+
+// Launch shape of the sweep kernel for windows of up to maxM steps: sites per
+// thread K, threads NT and time tiles T (workgroups per window, tiles of
+// S = NT K sites with (T-1) S < M <= T S).  Automatic choice: one workgroup
+// per window with the smallest K that keeps it within 256 threads (one wave
+// per SIMD, no register spills), else any single-workgroup shape; windows too
+// long for one workgroup are cut into tiles of 256 threads.
+int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles, int& NT, int& stage, int& T) {
   static const int cand32[] = {4, 8, 16};
   static const int cand64[] = {4, 8};
   const int* cand = fp64 ? cand64 : cand32;
   const int nc = fp64 ? 2 : 3;
-  for (int pass = 0; pass < 2; ++pass) {
+  const int want_T = allow_tiles ? ctx->tiles : 1;
+  if (want_T <= 1) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < nc; ++i) {
+        const int K = cand[i];
+        if (ctx->tile_K && ctx->tile_K != K) continue;
+        const int64_t need = (maxM + K - 1) / K;
+        const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
+        const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
+        if (nt > lim) continue;
+        const int64_t st = stage_room((int)nt, K, fp64);
+        if (st < 64) continue;
+        NT = (int)nt;
+        stage = (int)st;
+        T = 1;
+        return K;
+      }
+    }
+    if (want_T == 1 || !allow_tiles) return 0;
+  }
+  // FP64 windows are never cut into time tiles: that launch path faulted
+  // once on a 16-tile FP64 window without an identified cause, so it is
+  // refused here (FP64 is the small-window reference mode)
+  if (fp64) return 0;
+  // tiled: the requested T, or the fewest tiles of at most 256 threads
+  for (int Tt = want_T > 1 ? want_T : 2; Tt <= MAX_TILES; ++Tt) {
     for (int i = 0; i < nc; ++i) {
       const int K = cand[i];
       if (ctx->tile_K && ctx->tile_K != K) continue;
-      const int64_t need = (maxM + K - 1) / K;
-      const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
-      const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
-      if (nt > lim) continue;
-      const size_t base = pimc::sweep_smem_bytes((int)nt, K, fp64, 0) + pimc::LDS_STATIC_RESERVE;
-      if (base >= pimc::LDS_BYTES) continue;
-      const size_t ts = fp64 ? 8 : 4;
-      const int64_t room = (int64_t)((pimc::LDS_BYTES - base) / (4 * ts));
-      const int64_t st = std::min<int64_t>(nt * K + 1, room);
-      if (st < 64) continue;
-      NT = (int)nt;
-      stage = (int)st;
-      return K;
+      for (int nt = 256; nt >= 64; nt -= 64) {
+        const int64_t S = (int64_t)nt * K;
+        if (!((Tt - 1) * S < maxM && maxM <= Tt * S)) continue;
+        const int64_t st = stage_room(nt, K, fp64);
+        if (st < 64) continue;
+        NT = nt;
+        stage = (int)st;
+        T = Tt;
+        return K;
+      }
     }
+    if (want_T > 1) return 0;
   }
   return 0;
 }
@@ -161,6 +205,17 @@ int pimc_ctx_create(pimc_ctx** out, int device) {
     return PIMC_ERR_HIP;
   }
   if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
+  bool ok = hipMalloc(&c->halo, (size_t)MAX_TILES * 16 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->hflag, (size_t)MAX_TILES * 2 * sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(&c->wpart, (size_t)2 * MAX_TILES * 35 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->wsync, 16 * sizeof(uint32_t)) == hipSuccess;
+  int khz = 0;
+  ok = ok && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0;
+  if (!ok) {
+    pimc_ctx_destroy(c);
+    return PIMC_ERR_NOMEM;
+  }
+  c->spin_ticks = (uint64_t)khz * 1000ull * 4ull;   // a wait gives up after 4 s
   *out = c;
   return PIMC_OK;
 }
@@ -173,12 +228,22 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->offsets) (void)hipFree(ctx->offsets);
   if (ctx->order) (void)hipFree(ctx->order);
+  if (ctx->halo) (void)hipFree(ctx->halo);
+  if (ctx->hflag) (void)hipFree(ctx->hflag);
+  if (ctx->wpart) (void)hipFree(ctx->wpart);
+  if (ctx->wsync) (void)hipFree(ctx->wsync);
   delete ctx;
 }
 
 int pimc_set_sweep_tile(pimc_ctx* ctx, int K) {
   if (!ctx || !(K == 0 || K == 4 || K == 8 || K == 16)) return PIMC_ERR_ARG;
   ctx->tile_K = K;
+  return PIMC_OK;
+}
+
+int pimc_set_sweep_tiles(pimc_ctx* ctx, int T) {
+  if (!ctx || T < 0 || T > MAX_TILES) return PIMC_ERR_ARG;
+  ctx->tiles = T;
   return PIMC_OK;
 }
 
@@ -190,6 +255,7 @@ int pimc_sync(pimc_ctx* ctx, void* stream) {
   if (hipMemcpy(&e, ctx->err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess) return PIMC_ERR_HIP;
   if (e) {
     if (hipMemset(ctx->err, 0, sizeof(uint32_t)) != hipSuccess) return PIMC_ERR_HIP;
+    if (e & 4u) return PIMC_ERR_TIMEOUT;
     return (e & 2u) ? PIMC_ERR_BOX : PIMC_ERR_NONFINITE;
   }
   return PIMC_OK;
@@ -204,6 +270,7 @@ const char* pimc_strerror(int s) {
     case PIMC_ERR_UNSUPPORTED: return "shape not supported by the built kernels";
     case PIMC_ERR_NOMEM: return "out of device memory";
     case PIMC_ERR_BOX: return "state or parameter outside its box at entry";
+    case PIMC_ERR_TIMEOUT: return "a cross-tile wait timed out";
     default: return "unknown status";
   }
 }
@@ -259,13 +326,20 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   int r = model_args(model, a.m);
   if (r) return r;
   const bool fp64 = path->prec == PIMC_FP64;
-  int NT = 0, stage = 0;
-  const int K = choose_shape(ctx, path->M, fp64, NT, stage);
-  if (!K) return PIMC_ERR_UNSUPPORTED;
+  int NT = 0, stage = 0, T = 1;
   if (path->M >= (1ll << 30)) return PIMC_ERR_UNSUPPORTED;
+  const int K = choose_shape(ctx, path->M, fp64, true, NT, stage, T);
+  if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);
   a.stage = stage;
   a.stride = 1;
+  a.tiles = T;
+  a.ngroups = 1;
+  a.halo = ctx->halo;
+  a.hflag = ctx->hflag;
+  a.wpart = ctx->wpart;
+  a.wsync = ctx->wsync;
+  a.spin_ticks = ctx->spin_ticks;
   a.offsets = nullptr;
   a.M_single = path->M;
   a.X = path->X;
@@ -290,7 +364,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   fill_debug(a, debug);
   a.err = ctx->err;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
-  return pimc::launch_sweep(a, fp64, K, 1, NT, (hipStream_t)stream);
+  return pimc::launch_sweep(a, fp64, K, T, NT, (hipStream_t)stream);
 }
 
 int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
@@ -320,12 +394,14 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   int r = model_args(model, a.m);
   if (r) return r;
   const bool fp64 = b->prec == PIMC_FP64;
-  int NT = 0, stage = 0;
-  const int K = choose_shape(ctx, maxM, fp64, NT, stage);
+  int NT = 0, stage = 0, T = 1;
+  const int K = choose_shape(ctx, maxM, fp64, false, NT, stage, T);
   if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);
   a.stage = stage;
   a.stride = 1;
+  a.tiles = 1;
+  a.ngroups = B;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
   if ((r = ensure_batch(ctx, (size_t)B))) return r;
   // longest windows first, so the tail of the launch holds the short ones

@@ -43,7 +43,15 @@ struct SweepArgs {
   double* dbg_pprop;
   double* dbg_pdA;
   uint8_t* dbg_pacc;
-  uint32_t* err;  // bit 0: non-finite dA met, bit 1: entry state outside box
+  uint32_t* err;  // bit 0: non-finite dA met, bit 1: entry state outside box, bit 2: wait timed out
+  // time tiles (tiles == 1: a window is one workgroup, no global memory sync)
+  int32_t tiles;
+  int32_t ngroups;     // number of windows in the launch
+  void* halo;          // [ngroups*tiles][16] boundary sites (path precision)
+  uint32_t* hflag;     // [ngroups*tiles][2] generations of the first / last boundary site
+  double* wpart;       // [2][ngroups][tiles][35] partial sums of the parameter statistics
+  uint32_t* wsync;     // [ngroups][4]: arrival counter, entry-check flag
+  uint64_t spin_ticks; // wall-clock ticks a wait may last
 };
 
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage);

@@ -37,11 +37,22 @@ struct Nb {  // a neighbour site: state and cached F
   T F[4];
 };
 
-// Sum over eight neighbouring lanes (xor 1, 2, 4).
-__device__ __forceinline__ double oct_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
+// Move a double across lanes with one DPP control (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each row of 16 lanes with DPP (quad_perm xor 1, xor 2, then
+// row_ror 4 and 8); the row total lands in lanes 12..15 of the row.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x128>(v);  // row_ror:8
   return v;
 }
 
@@ -56,6 +67,33 @@ __device__ __forceinline__ bool accept_u(uint32_t uword, double dA) {
   if (gap > E) return true;
   if (gap < -E) return false;
   return ::log(u01_d(uword)) < -dA;
+}
+
+// Spin until *p >= target (agent-scope acquire).  Every wait is bounded: past
+// `ticks` of the constant wall clock the error flag gets bit 2 and the wait
+// gives up, so a workgroup can never wait forever on a missing partner.
+__device__ __forceinline__ void wait_ge(uint32_t* p, uint32_t target, uint32_t* err, uint64_t ticks) {
+  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > ticks) {
+        atomicOr(err, 4u);
+        break;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Barrier across the tiles of one window: a monotonic arrival counter.
+__device__ __forceinline__ void tile_barrier(uint32_t* cnt, uint32_t target, uint32_t* err, uint64_t ticks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    wait_ge(cnt, target, err, ticks);
+  }
+  __syncthreads();
 }
 
 // One Metropolis site update.  Returns true on accept (x, F replaced).
@@ -207,49 +245,52 @@ template <> struct ThetaMove<6> { static constexpr int ia = 6, ib = -1; };
 __host__ __device__ constexpr int symi(int a, int b) { return a <= b ? sym7(a, b) : sym7(b, a); }
 
 // One Metropolis move of parameter L against the sufficient statistics.
-// z: proposal step, uword: Philox word of the accept uniform (drawn beforehand).
+// z: proposal step; uword, lu32: Philox word of the accept uniform and its
+// FP32 logarithm (both drawn beforehand).  Written without branches except
+// the rare FP64 re-evaluation of log u near a tie, to keep the sequential
+// chain of the seven moves short.
 template <int L>
-__device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_t uword, const double (&wpar)[7],
-                                           double (&pd)[7], double (&s)[7], const double (&G)[28], bool& changed,
-                                           int& acc, int& nonfin, bool rec, int win) {
+__device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_t uword, float lu32,
+                                           const double (&wpar)[7], double (&pd)[7], double (&s)[7],
+                                           const double (&G)[28], bool& changed, int& acc, int& nonfin, bool rec,
+                                           int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
+  constexpr int ia = ThetaMove<L>::ia;
+  constexpr int ib = ThetaMove<L>::ib;
+  constexpr int ibb = ib >= 0 ? ib : 0;
   const double pl = pd[L] + wpar[L] * z;
-  double dA = __builtin_nan("");
-  bool ok = false;
-  if (pl >= a.m.p_lo[L] && pl <= a.m.p_hi[L]) {
-    constexpr int ia = ThetaMove<L>::ia;
-    constexpr int ib = ThetaMove<L>::ib;
-    constexpr int ibb = ib >= 0 ? ib : 0;
-    const double dp = pl - pd[L];
-    // p1, p2, p4, p6 move theta_L directly (and p2, p4, p6 also p_L p_{L+1});
-    // p3, p5, p7 move theta_L = p_{L-1} p_L
-    const double da = (L == 2 || L == 4 || L == 6) ? pd[L == 0 ? 0 : L - 1] * dp : dp;
-    const double db = ib >= 0 ? dp * pd[ibb] : 0.0;
-    double quad = da * da * G[symi(ia, ia)];
-    double lin = da * s[ia];
-    if (ib >= 0) {
-      quad += 2.0 * da * db * G[symi(ia, ibb)] + db * db * G[symi(ibb, ibb)];
-      lin += db * s[ibb];
-    }
-    dA = 0.5 * a.m.beta * a.m.Rd[0] * (quad - 2.0 * lin);
-    const bool fin = __builtin_isfinite(dA);
-    ok = fin && accept_u(uword, dA);
-    if (!fin) ++nonfin;
-    if (ok) {
-#pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        double gs = G[symi(j, ia)] * da;
-        if (ib >= 0) gs += G[symi(j, ibb)] * db;
-        s[j] -= gs;
-      }
-      pd[L] = pl;
-      changed = true;
-      ++acc;
-    }
+  const bool inbox = pl >= a.m.p_lo[L] && pl <= a.m.p_hi[L];
+  const double dp = pl - pd[L];
+  // p1, p2, p4, p6 move theta_L directly (p2, p4, p6 also p_L p_{L+1});
+  // p3, p5, p7 move theta_L = p_{L-1} p_L
+  const double da = (L == 2 || L == 4 || L == 6) ? pd[L == 0 ? 0 : L - 1] * dp : dp;
+  const double db = ib >= 0 ? dp * pd[ibb] : 0.0;
+  double quad = da * da * G[symi(ia, ia)];
+  double lin = da * s[ia];
+  if (ib >= 0) {
+    quad += 2.0 * da * db * G[symi(ia, ibb)] + db * db * G[symi(ibb, ibb)];
+    lin += db * s[ibb];
   }
+  const double dA = 0.5 * a.m.beta * a.m.Rd[0] * (quad - 2.0 * lin);
+  const bool fin = __builtin_isfinite(dA);
+  const double gap = -dA - (double)lu32;
+  const double E = 1e-5 * (1.0 + (double)__builtin_fabsf(lu32));
+  bool dec = gap > E;
+  if (__builtin_fabs(gap) <= E) dec = ::log(u01_d(uword)) < -dA;
+  const bool ok = inbox && fin && dec;
+  nonfin += (inbox && !fin) ? 1 : 0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    double gs = G[symi(j, ia)] * da;
+    if (ib >= 0) gs += G[symi(j, ibb)] * db;
+    s[j] = ok ? s[j] - gs : s[j];
+  }
+  pd[L] = ok ? pl : pd[L];
+  changed = changed || ok;
+  acc += ok ? 1 : 0;
   if (rec) {
     if (a.dbg_pprop) a.dbg_pprop[win * 7 + L] = pl;
-    if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = dA;
+    if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = inbox ? dA : __builtin_nan("");
     if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
   }
 }
@@ -266,7 +307,19 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   const int wv = t >> 6;
   const int NW = NT >> 6;
 
-  const int win = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  // block -> (window, tile): a window is split into a.tiles time tiles of
+  // S = NT K sites, one workgroup each
+  const int tiles = a.tiles;
+  const int bi = (int)blockIdx.x / tiles;
+  int tb = (int)blockIdx.x - bi * tiles;
+  // workgroups are dealt to the 8 XCDs round-robin (block b -> XCD b % 8);
+  // when the tile count allows, consecutive tiles are given consecutive
+  // blocks of one XCD, so most boundary exchanges stay inside one L2
+  if (tiles % 8 == 0 && tiles > 8) tb = (tb % 8) * (tiles / 8) + tb / 8;
+  const int win = a.order ? a.order[bi] : bi;
+  const int S = NT * K;
+  const int tile0 = tb * S;
+  const bool last_tile = tb == tiles - 1;
   int64_t base = 0;
   int M = (int)a.M_single;
   if (a.offsets) {
@@ -280,11 +333,11 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   // ---- LDS ----------------------------------------------------------------
   T* lfirst = (T*)smem;                           // [NT][8] first site of each thread
   T* llast = lfirst + NT * 8;                     // [NT][8] last site of each thread
-  T* lyi = llast + NT * 8;                        // [NT*K+1][2] (y_n, I_n) of the window
-  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [NRED][8*NW] partials of 8 lanes
-  double* lstat = lred + NRED * 8 * NW;           // [NRED]
-  double* ldraw = lstat + NRED;                   // [16]: z_l, log u_l of the parameter moves
-  int* lcnt = (int*)(ldraw + 16);                 // [16]
+  T* lyi = llast + NT * 8;                        // [S+2][2] (y_n, I_n), n = tile0-1 .. tile0+S
+  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [NRED][4*NW] row partials
+  double* lstat = lred + NRED * 4 * NW;           // [NRED]
+  double* ldraw = lstat + NRED;                   // [24]: z_l, accept word, FP32 log u_l
+  int* lcnt = (int*)(ldraw + 24);                 // [16]
   T* lstage = (T*)(lcnt + 16);                    // [stage][4] statistics staging
 
   Consts<T> C;
@@ -305,22 +358,39 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   const bool uniform_prop = a.m.proposal == PIMC_PROP_UNIFORM;
   const double hD = 0.5 * a.m.dt;
 
-  // observations and drive of the whole window -> LDS
+  // observations and drive of the tile and its two halo sites -> LDS;
+  // lyb[2 n], lyb[2 n + 1] address (y_n, I_n) by global site index
+  T* lyb = lyi + 2 * (1 - tile0);
   {
     const T* Yw = (const T*)a.y + base;
     const T* Iw = (const T*)a.I + base;
-    for (int n = t; n <= M; n += NT) {
-      lyi[2 * n] = Yw[n];
-      lyi[2 * n + 1] = Iw[n];
+    const int lo = tile0 > 0 ? tile0 - 1 : 0;
+    const int hi = min(M, tile0 + S);
+    for (int n = lo + t; n <= hi; n += NT) {
+      lyb[2 * n] = Yw[n];
+      lyb[2 * n + 1] = Iw[n];
     }
   }
 
   // ---- own sites: n = n0 + j, j < K, plus site M on the last thread when
   //      the regular slots stop exactly at M ------------------------------
-  const int NTneed = (M + K - 1) / K;
+  const int NTneed = last_tile ? (M - tile0 + K - 1) / K : NT;
   const bool active = t < NTneed;
-  const int n0 = t * K;
-  const bool has_extra = (t == NTneed - 1) && (K * NTneed == M);
+  const int n0 = tile0 + t * K;
+  const bool has_extra = last_tile && (t == NTneed - 1) && (K * NTneed == M - tile0);
+  // cross-tile halo: boundary sites of each tile in global memory
+  const int gt = bi * tiles + tb;                 // global tile index
+  // [0..7] first, [8..15] last site; a single-tile window never touches it
+  // (it then points at this workgroup's own LDS exchange slot)
+  T* hmine = (tiles > 1 && a.halo) ? (T*)a.halo + (int64_t)gt * 16 : lfirst + t * 8;
+  // neighbouring tiles' halo slots; where a neighbour does not exist they
+  // alias this tile's own slot, so every address formed is a valid one
+  const T* hprev = tb > 0 ? (const T*)a.halo + (int64_t)(gt - 1) * 16 : hmine;
+  const T* hnext = !last_tile ? (const T*)a.halo + (int64_t)(gt + 1) * 16 : hmine;
+  // LDS index of the extra site's (y, I): site M when this thread owns it,
+  // else the tile's first site, so that no evaluation of the expression
+  // (speculative or not) leaves the tile's LDS block
+  const int me = has_extra ? M : tile0;
   T* Xt = (T*)a.X + (base + n0) * 4;
   __syncthreads();
 
@@ -332,15 +402,19 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     const bool v = active && n0 + j <= M;
 #pragma unroll
     for (int c = 0; c < 4; ++c) x[j][c] = v ? Xt[j * 4 + c] : C.lo[c];
-    hh_F(C, x[j], v ? lyi[2 * (n0 + j) + 1] : (T)0, F[j]);
+    hh_F(C, x[j], v ? lyb[2 * (n0 + j) + 1] : (T)0, F[j]);
     if (v) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) bad = bad || !(x[j][c] >= C.lo[c] && x[j][c] <= C.hi[c]);
     }
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) xe[c] = has_extra ? Xt[K * 4 + c] : C.lo[c];
-  hh_F(C, xe, has_extra ? lyi[2 * M + 1] : (T)0, Fe);
+  for (int c = 0; c < 4; ++c) xe[c] = C.lo[c];
+  if (has_extra) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xe[c] = Xt[K * 4 + c];
+  }
+  hh_F(C, xe, has_extra ? lyb[2 * me + 1] : (T)0, Fe);
   if (has_extra) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) bad = bad || !(xe[c] >= C.lo[c] && xe[c] <= C.hi[c]);
@@ -352,6 +426,18 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       if ((a.m.p_mask >> l) & 1) bad = bad || !(pd[l] >= a.m.p_lo[l] && pd[l] <= a.m.p_hi[l]);
     }
   }
+  if (tiles > 1) {
+    // every tile learns whether any tile failed the entry check, and the
+    // boundary sites are published before the first sweep
+    if (__syncthreads_or(bad) && t == 0) atomicOr(&a.wsync[bi * 4 + 1], 1u);
+    if (t == 0) lds_put(hmine, x[0], F[0]);
+    if (t == NT - 1 && !last_tile) {
+      lds_put(hmine + 8, x[K - 1], F[K - 1]);
+      __hip_atomic_store(&a.hflag[gt * 2 + 1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    tile_barrier(&a.wsync[bi * 4], (uint32_t)tiles, a.err, a.spin_ticks);
+    bad = __hip_atomic_load(&a.wsync[bi * 4 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  }
   if (__syncthreads_or(bad)) {
     if (t == 0) atomicOr(a.err, 2u);
     return;
@@ -361,6 +447,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     lds_put(llast + t * 8, x[K - 1], F[K - 1]);
   }
   __syncthreads();
+  uint32_t nbar = 1;   // tile barriers passed so far (the entry barrier)
 
   int accE = 0, accO = 0, nonfin = 0;
   int accP[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -390,7 +477,14 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             Nb<T> L, R;
             const bool hasL = nn >= 1;
             if (j == 0) {
-              if (hasL) lds_get(C, llast + (t - 1) * 8, lyi[2 * nn - 1], L);
+              if (hasL) {
+                if (t == 0) {   // last site of the previous tile, after its odd half-sweep
+                  wait_ge(&a.hflag[(gt - 1) * 2 + 1], (uint32_t)it + 1, a.err, a.spin_ticks);
+                  lds_get(C, hprev + 8, lyb[2 * nn - 1], L);
+                } else {
+                  lds_get(C, llast + (t - 1) * 8, lyb[2 * nn - 1], L);
+                }
+              }
             } else {
 #pragma unroll
               for (int c = 0; c < 4; ++c) {
@@ -407,7 +501,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
             double dA;
             T xp[4];
-            const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyi[2 * nn], lyi[2 * nn + 1], hasL, L,
+            const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyb[2 * nn], lyb[2 * nn + 1], hasL, L,
                                         hasR, R, nn >= 1, blk, jj == 0 ? ub.x : ub.z, dA, xp, nonfin);
             accE += ok;
             if (DBG && last) {
@@ -433,7 +527,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         const U4 ub = draw(key, opaque((uint32_t)(M >> 2)), k, TAG_SACC);
         double dA;
         T xp[4];
-        const bool ok = site_update(C, ws, uniform_prop, xe, Fe, lyi[2 * M], lyi[2 * M + 1], true, L, false, R,
+        const bool ok = site_update(C, ws, uniform_prop, xe, Fe, lyb[2 * me], lyb[2 * me + 1], true, L, false, R,
                                     true, blk, ub.x, dA, xp, nonfin);
         accE += ok;
         if (DBG && last) {
@@ -445,6 +539,10 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         }
       }
       if (active) lds_put(lfirst + t * 8, x[0], F[0]);
+      if (tiles > 1 && t == 0) {
+        lds_put(hmine, x[0], F[0]);
+        __hip_atomic_store(&a.hflag[gt * 2], (uint32_t)it + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
       __syncthreads();
 
       // ---- odd half-sweep -----------------------------------------------
@@ -467,8 +565,11 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
                   R.x[c] = xe[c];
                   R.F[c] = Fe[c];
                 }
+              } else if (t == NT - 1) {   // first site of the next tile, after its even half-sweep
+                wait_ge(&a.hflag[(gt + 1) * 2], (uint32_t)it + 1, a.err, a.spin_ticks);
+                lds_get(C, hnext, lyb[2 * nn + 3], R);
               } else {
-                lds_get(C, lfirst + (t + 1) * 8, lyi[2 * nn + 3], R);
+                lds_get(C, lfirst + (t + 1) * 8, lyb[2 * nn + 3], R);
               }
             }
           } else {
@@ -481,7 +582,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
           double dA;
           T xp[4];
-          const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyi[2 * nn], lyi[2 * nn + 1], true, L,
+          const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyb[2 * nn], lyb[2 * nn + 1], true, L,
                                       hasR, R, true, blk, uodd[j >> 1], dA, xp, nonfin);
           accO += ok;
           if (DBG && last) {
@@ -494,6 +595,10 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         }
       }
       if (active) lds_put(llast + t * 8, x[K - 1], F[K - 1]);
+      if (tiles > 1 && t == NT - 1 && !last_tile) {
+        lds_put(hmine + 8, x[K - 1], F[K - 1]);
+        __hip_atomic_store(&a.hflag[gt * 2 + 1], (uint32_t)it + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
 
     if (a.flags & PIMC_PARAMS) {
@@ -516,6 +621,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           }
           ldraw[l] = z;
           ldraw[8 + l] = __builtin_bit_cast(double, (uint64_t)b.z);
+          ldraw[16 + l] = (double)(__builtin_amdgcn_logf(u01_f(b.z)) * 0.6931471805599453f);
         }
       }
       // ---- sufficient statistics over the links of the odd sites ----------
@@ -525,26 +631,34 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #pragma unroll
       for (int i = 0; i < NRED; ++i) st[i] = 0.0;
       if (active) {
-        Feat fl = feat_of(x[0], lyi[2 * n0 + 1]);
+        Feat fl = feat_of(x[0], lyb[2 * n0 + 1]);
 #pragma unroll
         for (int j = 1; j < K; j += 2) {
           const int nn = n0 + j;
           if (nn <= M) {
-            const Feat fc = feat_of(x[j], lyi[2 * nn + 1]);
+            const Feat fc = feat_of(x[j], lyb[2 * nn + 1]);
             link_stats(th, hD, fl, fc, st);
             if (nn + 1 <= M) {
               Feat fr;
               if (j == K - 1) {
                 if (has_extra) {
-                  fr = feat_of(xe, lyi[2 * M + 1]);
+                  fr = feat_of(xe, lyb[2 * me + 1]);
                 } else {
+                  // next thread's first site, or the next tile's (already
+                  // awaited during the odd half-sweep when sites moved)
+                  const T* src = lfirst + (t + 1) * 8;
+                  if (t == NT - 1) {
+                    // without site moves the entry publication is current
+                    if (a.flags & PIMC_STATES) wait_ge(&a.hflag[(gt + 1) * 2], (uint32_t)it + 1, a.err, a.spin_ticks);
+                    src = hnext;
+                  }
                   T xr[4];
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) xr[c] = lfirst[(t + 1) * 8 + c];
-                  fr = feat_of(xr, lyi[2 * nn + 3]);
+                  for (int c = 0; c < 4; ++c) xr[c] = src[c];
+                  fr = feat_of(xr, lyb[2 * nn + 3]);
                 }
               } else {
-                fr = feat_of(x[j + 1], lyi[2 * nn + 3]);
+                fr = feat_of(x[j + 1], lyb[2 * nn + 3]);
               }
               link_stats(th, hD, fc, fr, st);
               fl = fr;
@@ -552,19 +666,19 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           }
         }
       }
-      // ---- block reduction: groups of 8 lanes in registers, then a
-      //      fixed-order sum of the group partials through LDS -------------
+      // ---- block reduction: rows of 16 lanes with DPP, then a fixed-order
+      //      sum of the row partials through LDS --------------------------
 #pragma unroll
-      for (int i = 0; i < NRED; ++i) st[i] = oct_sum(st[i]);
-      if ((lane & 7) == 0) {
+      for (int i = 0; i < NRED; ++i) st[i] = row_sum(st[i]);
+      if ((lane & 15) == 15) {
 #pragma unroll
-        for (int i = 0; i < NRED; ++i) lred[i * 8 * NW + wv * 8 + (lane >> 3)] = st[i];
+        for (int i = 0; i < NRED; ++i) lred[i * 4 * NW + wv * 4 + (lane >> 4)] = st[i];
       }
       __syncthreads();
       if (t < NRED) {
-        const double* row = lred + t * 8 * NW;
+        const double* row = lred + t * 4 * NW;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int q = 0; q < 8 * NW; q += 4) {
+        for (int q = 0; q < 4 * NW; q += 4) {
           s0 += row[q];
           s1 += row[q + 1];
           s2 += row[q + 2];
@@ -573,35 +687,73 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         lstat[t] = (s0 + s1) + (s2 + s3);
       }
       __syncthreads();
+      if (tiles > 1) {
+        // all-reduce over the window's tiles: partials in a double buffer,
+        // summed in tile order by every tile (identical results everywhere)
+        double* wp = a.wpart + ((int64_t)(nbar & 1) * a.ngroups * tiles + (int64_t)bi * tiles) * NRED;
+        if (t < NRED) wp[tb * NRED + t] = lstat[t];
+        ++nbar;
+        tile_barrier(&a.wsync[bi * 4], nbar * (uint32_t)tiles, a.err, a.spin_ticks);
+        // NRED x tiles partials: thread t sums tiles q = t / NRED, + NSEG, ...
+        // for value t % NRED with all loads in flight, then NSEG segment sums
+        // are combined in segment order (fixed for a given launch shape)
+        {
+          const int NSEG = NT / NRED;
+          const int v = t % NRED, sg = t / NRED;
+          if (sg < NSEG) {
+            double acc = 0.0;
+            for (int q0 = sg; q0 < tiles; q0 += 8 * NSEG) {
+              double vals[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u * NSEG;
+                vals[u] = q < tiles ? wp[q * NRED + v] : 0.0;
+              }
+#pragma unroll
+              for (int u = 0; u < 8; ++u) acc += vals[u];
+            }
+            lred[sg * NRED + v] = acc;
+          }
+          __syncthreads();
+          if (t < NRED) {
+            double acc = 0.0;
+            for (int q = 0; q < NSEG; ++q) acc += lred[q * NRED + t];
+            lstat[t] = acc;
+          }
+        }
+        __syncthreads();
+      }
       // ---- sequential parameter moves, evaluated identically by every
       //      wave (no broadcast and no further barrier needed) ---------------
       {
         double s7[7], G[28], zz[7];
         uint32_t uw[7];
+        float lw[7];
 #pragma unroll
         for (int l = 0; l < 7; ++l) {
           s7[l] = lstat[l];
           zz[l] = ldraw[l];
           uw[l] = (uint32_t)__builtin_bit_cast(uint64_t, ldraw[8 + l]);
+          lw[l] = (float)ldraw[16 + l];
         }
 #pragma unroll
         for (int i = 0; i < 28; ++i) G[i] = lstat[7 + i];
         bool changed = false;
-        const bool rec = last && t == 0;
-        param_move<0>(a, zz[0], uw[0], wpar, pd, s7, G, changed, accP[0], nonfin, rec, win);
-        param_move<1>(a, zz[1], uw[1], wpar, pd, s7, G, changed, accP[1], nonfin, rec, win);
-        param_move<2>(a, zz[2], uw[2], wpar, pd, s7, G, changed, accP[2], nonfin, rec, win);
-        param_move<3>(a, zz[3], uw[3], wpar, pd, s7, G, changed, accP[3], nonfin, rec, win);
-        param_move<4>(a, zz[4], uw[4], wpar, pd, s7, G, changed, accP[4], nonfin, rec, win);
-        param_move<5>(a, zz[5], uw[5], wpar, pd, s7, G, changed, accP[5], nonfin, rec, win);
-        param_move<6>(a, zz[6], uw[6], wpar, pd, s7, G, changed, accP[6], nonfin, rec, win);
+        const bool rec = last && t == 0 && tb == 0;
+        param_move<0>(a, zz[0], uw[0], lw[0], wpar, pd, s7, G, changed, accP[0], nonfin, rec, win);
+        param_move<1>(a, zz[1], uw[1], lw[1], wpar, pd, s7, G, changed, accP[1], nonfin, rec, win);
+        param_move<2>(a, zz[2], uw[2], lw[2], wpar, pd, s7, G, changed, accP[2], nonfin, rec, win);
+        param_move<3>(a, zz[3], uw[3], lw[3], wpar, pd, s7, G, changed, accP[3], nonfin, rec, win);
+        param_move<4>(a, zz[4], uw[4], lw[4], wpar, pd, s7, G, changed, accP[4], nonfin, rec, win);
+        param_move<5>(a, zz[5], uw[5], lw[5], wpar, pd, s7, G, changed, accP[5], nonfin, rec, win);
+        param_move<6>(a, zz[6], uw[6], lw[6], wpar, pd, s7, G, changed, accP[6], nonfin, rec, win);
         if (changed) {
 #pragma unroll
           for (int l = 0; l < 7; ++l) pd[l] = wave_uniform(pd[l]);
           C.set_p(pd);
 #pragma unroll
-          for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], lyi[2 * (n0 + j) + 1]);
-          Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], has_extra ? lyi[2 * M + 1] : (T)0);
+          for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], lyb[2 * (n0 + j) + 1]);
+          Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], has_extra ? lyb[2 * me + 1] : (T)0);
         }
       }
     } else {
@@ -609,7 +761,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     }
 
     // ---- statistics ------------------------------------------------------
-    if (a.ptrace && t == 0) {
+    if (a.ptrace && t == 0 && tb == 0) {
 #pragma unroll
       for (int l = 0; l < 7; ++l) a.ptrace[(int64_t)win * a.n_sweeps * 7 + it * 7 + l] = pd[l];
     }
@@ -619,24 +771,25 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       const T* xr = (const T*)a.xref + base * 4;
       double* su = a.sum + base * 4;
       double* sq = a.sumsq ? a.sumsq + base * 4 : nullptr;
-      const int S = a.stage;
-      for (int c0 = 0; c0 <= M; c0 += S) {
+      const int Sst = a.stage;
+      const int hi_site = last_tile ? M : tile0 + S - 1;   // this tile's sites only
+      for (int c0 = tile0; c0 <= hi_site; c0 += Sst) {
         if (active) {
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const int n = n0 + j;
-            if (n <= M && n >= c0 && n < c0 + S) {
+            if (n <= M && n >= c0 && n < c0 + Sst) {
 #pragma unroll
               for (int c = 0; c < 4; ++c) lstage[(n - c0) * 4 + c] = x[j][c];
             }
           }
-          if (has_extra && M >= c0 && M < c0 + S) {
+          if (has_extra && M >= c0 && M < c0 + Sst) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) lstage[(M - c0) * 4 + c] = xe[c];
           }
         }
         __syncthreads();
-        const int cnt = 4 * min(S, M + 1 - c0);
+        const int cnt = 4 * min(Sst, hi_site + 1 - c0);
         // eight independent elements per round: all loads are in flight
         // before the first add, so the loop is bandwidth- not latency-bound
         for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
@@ -676,7 +829,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) Xt[K * 4 + c] = xe[c];
   }
-  if (t == 0) {
+  if (t == 0 && tb == 0) {
 #pragma unroll
     for (int l = 0; l < 7; ++l) P[l] = pd[l];
   }
@@ -687,9 +840,9 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   if (accE) atomicAdd(&lcnt[0], accE);
   if (accO) atomicAdd(&lcnt[1], accO);
   if (nonfin && lane != 0) atomicAdd(&lcnt[9], nonfin);
-  if (t == 0) {
+  if (t == 0 && tb == 0) {
     // parameter counts (and their non-finite count) are identical in every
-    // wave; lane 0 of wave 0 reports them once
+    // wave and every tile; lane 0 of wave 0 of tile 0 reports them once
 #pragma unroll
     for (int l = 0; l < 7; ++l) lcnt[2 + l] += accP[l];
     if (nonfin) atomicAdd(&lcnt[9], nonfin);
@@ -707,8 +860,13 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
   const size_t ts = fp64 ? 8 : 4;
   const size_t NW = (size_t)NT / 64;
-  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 8 * NW + NRED + 16) * sizeof(double) +
+  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 24) * sizeof(double) +
          16 * sizeof(int) + (size_t)stage * 4 * ts;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // The launch is refused on the host (never enqueued) when the kernel's static
@@ -721,6 +879,18 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
   if (hipGetDevice(&dev) != hipSuccess) return PIMC_ERR_HIP;
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
   if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
+  if (a.tiles > 1) {
+    // tiles wait on each other: reset their flags and counters in stream
+    // order, then launch cooperatively so that every tile is resident
+    const int nf = nblocks * 2, nw = a.ngroups * 4;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.hflag, nf);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, a.wsync, nw);
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    const hipError_t e = hipLaunchCooperativeKernel((const void*)k, dim3(nblocks), dim3(NT), args, (unsigned)sm, s);
+    if (e == hipErrorCooperativeLaunchTooLarge) return PIMC_ERR_UNSUPPORTED;
+    return e == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
+  }
   hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), sm, s, a);
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }

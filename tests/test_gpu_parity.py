@@ -56,15 +56,18 @@ def _oracle_one_sweep(prob, X, p, sweep, chain=0, flags=3):
     return X, p, dbg, st
 
 
-def _gpu_one_sweep(ctx, prob, X, p, sweep, prec, chain=0, flags=3):
+def _gpu_one_sweep(ctx, prob, X, p, sweep, prec, chain=0, flags=3, tiles=0):
+    ctx.set_tiles(tiles)
     win = P.Window.from_arrays(X, p, prob.y, prob.I, prec)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     dbg = P.SweepDebug.allocate(win)
     st = P.SweepStats.allocate(win, 1, moments=False)
-    print(f"gpu sweep prec={prec} M={prob.M} sweep={sweep} flags={flags}", flush=True)
+    print(f"gpu sweep prec={prec} M={prob.M} sweep={sweep} flags={flags} tiles={tiles}", flush=True)
     P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=chain, sweep0=sweep, w=w, n_sweeps=1,
                  flags=flags, stats=st, debug=dbg)
-    assert ctx.sync() == 0
+    rc = ctx.sync()
+    ctx.set_tiles(0)
+    assert rc == 0
     return win, dbg, st
 
 
@@ -124,14 +127,24 @@ def _check_sites(gdbg, odbg, tol, margin_of):
     return int((~safe).sum())
 
 
-@pytest.mark.parametrize("M", [1, 2, 8, 9, 37, 256, 300, 1000, 4096])
-def test_sweep_fp64_lockstep(ctx, M):
+FP64_TILES_OFF = pytest.mark.skip(
+    reason="FP64 time tiles are switched off: a 16-tile FP64 window faulted the GPU once (memory aperture "
+           "violation) and no cause has been shown yet; the library refuses FP64 tiled shapes")
+
+
+@pytest.mark.parametrize("M,tiles", [(1, 0), (2, 0), (8, 0), (9, 0), (37, 0), (256, 0), (300, 0), (1000, 0),
+                                     (4096, 0),
+                                     pytest.param(1000, 2, marks=FP64_TILES_OFF),
+                                     pytest.param(1000, 4, marks=FP64_TILES_OFF),
+                                     pytest.param(4096, 16, marks=FP64_TILES_OFF),
+                                     pytest.param(2049, 9, marks=FP64_TILES_OFF)])
+def test_sweep_fp64_lockstep(ctx, M, tiles):
     prob = _problem(M)
     X = _perturbed(prob, 3)
     p = prob.p_true * 1.01
     for sweep in (0, 12345678901):
         Xo, po, od, so = _oracle_one_sweep(prob, X, p, sweep)
-        win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, sweep, "fp64")
+        win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, sweep, "fp64", tiles=tiles)
         np.testing.assert_allclose(gd.xprop.cpu().numpy(), od.xprop, rtol=1e-14, atol=1e-14)
         ties = _check_sites(gd, od, 1e-12, lambda d: 1e-6)
         gpdA = gd.pdA.cpu().numpy()
@@ -145,14 +158,14 @@ def test_sweep_fp64_lockstep(ctx, M):
             np.testing.assert_array_equal(gs.acc.cpu().numpy(), so.acc)
 
 
-@pytest.mark.parametrize("M", [8, 37, 256, 4096, 8192])
-def test_sweep_fp32_site_parity(ctx, M):
-    prob = _problem(M)
+@pytest.mark.parametrize("M,tiles", [(8, 0), (37, 0), (256, 0), (4096, 0), (8192, 0), (4096, 4), (65536, 0)])
+def test_sweep_fp32_site_parity(ctx, M, tiles):
+    prob = _problem(M, dt=0.01 if M > 8192 else 0.02)
     X = _perturbed(prob, 4).astype(np.float32).astype(np.float64)
     p = prob.p_true * 0.99
     y32 = prob.y.astype(np.float32).astype(np.float64)
     I32 = prob.I.astype(np.float32).astype(np.float64)
-    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 77, "fp32", flags=P._lib.PIMC_STATES)
+    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 77, "fp32", flags=P._lib.PIMC_STATES, tiles=tiles)
     xp = gd.xprop.cpu().numpy().astype(np.float64)
     # proposals: same Philox words, FP32 Box-Muller vs FP64
     Xo, po, od, so = _oracle_one_sweep(prob, X, p, 77, flags=OS.STATES)
@@ -264,6 +277,35 @@ def test_tiling_invariance_fp32(ctx):
         np.testing.assert_allclose(p, outs[0][1], rtol=1e-14)
 
 
+@pytest.mark.parametrize("M", [4096, 65536])
+def test_time_tiles_give_the_same_chain(ctx, M):
+    """Cutting the window into time tiles (halo exchange + cross-tile
+    all-reduce) leaves the chain unchanged: site updates are bit-identical,
+    parameter decisions equal (the reduction order differs only in rounding)."""
+    prob = _problem(M, dt=0.01 if M > 8192 else 0.02)
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    outs = []
+    choices = (1, 2, 4, 16) if M == 4096 else (0, 32, 64)
+    n = 20 if M == 4096 else 4
+    for T in choices:
+        ctx.set_tiles(T)
+        win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+        st = P.SweepStats.allocate(win, n, burn=0)
+        print(f"tiles={T} M={M}", flush=True)
+        P.pimc_sweep(ctx, prob.model, win, seed=21, chain=2, sweep0=5, w=w, n_sweeps=n, stats=st)
+        rc = ctx.sync()
+        ctx.set_tiles(0)
+        assert rc == 0
+        outs.append((win.X.cpu().numpy(), win.p.cpu().numpy(), st.acc.cpu().numpy(), st.sum.cpu().numpy(),
+                     st.ptrace.cpu().numpy()))
+    for X, p, acc, su, tr in outs[1:]:
+        np.testing.assert_array_equal(X, outs[0][0])
+        np.testing.assert_allclose(p, outs[0][1], rtol=1e-14)
+        np.testing.assert_array_equal(acc, outs[0][2])
+        np.testing.assert_allclose(su, outs[0][3], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(tr, outs[0][4], rtol=1e-14)
+
+
 def test_batch_window_equals_single_run(ctx):
     Ms = [37, 300, 64, 129]
     probs = [W.make_hh_problem(M, 0.02, 200 + i, require_spike=False) for i, M in enumerate(Ms)]
@@ -332,15 +374,53 @@ def test_nonfinite_data_reported(ctx):
 
 
 def test_oversized_window_refused_on_host(ctx):
-    """A window whose LDS footprint exceeds the CU's LDS is refused before
-    anything is enqueued, and the context stays usable."""
+    """A window whose LDS footprint exceeds the CU's LDS, with time tiles
+    disabled, is refused before anything is enqueued; the context stays
+    usable."""
     prob = _problem(16384, init="truth")
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
     w = P.widths_tensor(prob.w_state, prob.w_param)
-    with pytest.raises(P._lib.PimcError) as e:
-        P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    ctx.set_tiles(1)
+    try:
+        with pytest.raises(P._lib.PimcError) as e:
+            P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    finally:
+        ctx.set_tiles(0)
     assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
     assert ctx.sync() == 0
     small = P.Window.from_arrays(prob.X0[:65], prob.p0, prob.y[:65], prob.I[:65], "fp64")
     P.pimc_sweep(ctx, prob.model, small, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
     assert ctx.sync() == 0
+
+
+def test_long_fp64_window_refused(ctx):
+    """FP64 windows longer than one workgroup are refused on the host."""
+    prob = _problem(16384, init="truth")
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    for T in (0, 16):
+        ctx.set_tiles(T)
+        try:
+            with pytest.raises(P._lib.PimcError) as e:
+                P.pimc_sweep(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+        finally:
+            ctx.set_tiles(0)
+        assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
+    assert ctx.sync() == 0
+
+
+@FP64_TILES_OFF
+def test_long_fp64_window_auto_tiled_lockstep(ctx):
+    """FP64 window too long for one workgroup: cut into 16 tiles of 256
+    threads automatically, one sweep in lockstep with the oracle."""
+    prob = _problem(16384)
+    X = _perturbed(prob, 9)
+    p = prob.p_true * 1.005
+    Xo, po, od, so = _oracle_one_sweep(prob, X, p, 3)
+    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 3, "fp64", tiles=0)
+    ties = _check_sites(gd, od, 1e-12, lambda d: 1e-6)
+    m = np.isfinite(od.pdA)
+    np.testing.assert_allclose(gd.pdA.cpu().numpy()[m], od.pdA[m], rtol=1e-9, atol=1e-9)
+    if ties == 0:
+        np.testing.assert_allclose(win.X.cpu().numpy(), Xo, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(win.p.cpu().numpy(), po, rtol=1e-14)

@@ -216,6 +216,31 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* bat
                    uint64_t seed, uint64_t sweep0, const double* w, int64_t n_sweeps,
                    int32_t flags, const pimc_batch_stats* stats, void* stream);
 
+/* Statistics of pimc_hmc (every pointer nullable; device memory).
+ *   acc     [B][PIMC_NACC] int64 (+=): [0] accepted proposals, [1] proposals
+ *           whose trajectory left the box, [9] non-finite energy changes
+ *   ptrace  [B][n_proposals][7] FP64: p after every proposal (written)
+ *   dH      [B][n_proposals] FP64: H1 - H0 of every proposal (written) */
+typedef struct {
+  int64_t* acc;
+  double* ptrace;
+  double* dH;
+} pimc_hmc_stats;
+
+/* n_proposals Hybrid Monte Carlo proposals (the Hybrid MC of Section 3, a
+ * derivative-based proposal in the sense of Section 3.1) for every window of
+ * a packed batch, on the coordinates (X, sampled p):
+ *   momenta r ~ N(0, 1/minv) (Philox MOM / PMOM addresses of proposal k),
+ *   L leapfrog steps of size eps driven by dA/d(X, p) (the local stencil of
+ *   pimc_grad), H = A + 1/2 sum r^2 minv in FP64, accept iff log u < -dH
+ *   (u at the HACC address) and no position left the box at any step.
+ * Proposal indices are k0 .. k0 + n_proposals - 1.  minv: HOST FP64 [11],
+ * inverse masses of (V, m, h, n) then p1..p7 (unsampled parameters never
+ * move).  eps > 0, L >= 1.  Positions and parameters are updated in place. */
+int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* batch, uint64_t seed, uint64_t k0,
+             double eps, int32_t L, const double* minv, int64_t n_proposals, const pimc_hmc_stats* stats,
+             void* stream);
+
 #ifdef __cplusplus
 }
 #endif

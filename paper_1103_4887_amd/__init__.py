@@ -8,8 +8,8 @@ libpimc.so (C ABI in include/pimc.h); this package only binds it.
 """
 
 from . import _lib
-from .api import (Context, PackedBatch, SweepDebug, SweepStats, Window, model_struct, pimc_action,
-                  pimc_grad, pimc_param_update, pimc_run_batch, pimc_sweep, widths_tensor)
+from .api import (Context, HmcStats, PackedBatch, SweepDebug, SweepStats, Window, model_struct, pimc_action,
+                  pimc_grad, pimc_hmc, pimc_param_update, pimc_run_batch, pimc_sweep, widths_tensor)
 
-__all__ = ["Context", "PackedBatch", "SweepDebug", "SweepStats", "Window", "model_struct", "pimc_action",
+__all__ = ["Context", "HmcStats", "pimc_hmc", "PackedBatch", "SweepDebug", "SweepStats", "Window", "model_struct", "pimc_action",
            "pimc_grad", "pimc_param_update", "pimc_run_batch", "pimc_sweep", "widths_tensor", "_lib"]

@@ -65,6 +65,10 @@ class BatchStats(C.Structure):
                 ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64)]
 
 
+class HmcStats(C.Structure):
+    _fields_ = [("acc", C.c_void_p), ("ptrace", C.c_void_p), ("dH", C.c_void_p)]
+
+
 _SIGS = {
     "pimc_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "pimc_ctx_destroy": (None, [C.c_void_p]),
@@ -81,6 +85,8 @@ _SIGS = {
                             C.c_void_p]),
     "pimc_run_batch": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Batch), C.c_uint64, C.c_uint64,
                                  C.c_void_p, C.c_int64, C.c_int32, C.POINTER(BatchStats), C.c_void_p]),
+    "pimc_hmc": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Batch), C.c_uint64, C.c_uint64, C.c_double,
+                           C.c_int32, C.POINTER(C.c_double), C.c_int64, C.POINTER(HmcStats), C.c_void_p]),
 }
 
 _lib = None

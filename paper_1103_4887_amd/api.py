@@ -291,3 +291,32 @@ def pimc_run_batch(ctx: Context, spec, batch: PackedBatch, *, seed: int, sweep0:
         st = C.byref(bs)
     L.check(ctx.lib.pimc_run_batch(ctx.h, C.byref(m), C.byref(b), int(seed), int(sweep0), _ptr(w),
                                    int(n_sweeps), int(flags), st, _stream(stream)), "pimc_run_batch")
+
+
+@dataclass
+class HmcStats:
+    acc: Optional[torch.Tensor] = None      # [B][10] int64
+    ptrace: Optional[torch.Tensor] = None   # [B][n][7]
+    dH: Optional[torch.Tensor] = None       # [B][n]
+
+    @staticmethod
+    def allocate(B: int, n: int, device="cuda"):
+        return HmcStats(acc=torch.zeros((B, L.PIMC_NACC), dtype=torch.int64, device=device),
+                        ptrace=torch.zeros((B, n, 7), dtype=torch.float64, device=device),
+                        dH=torch.zeros((B, n), dtype=torch.float64, device=device))
+
+    def struct(self) -> L.HmcStats:
+        s = L.HmcStats()
+        s.acc, s.ptrace, s.dH = _ptr(self.acc), _ptr(self.ptrace), _ptr(self.dH)
+        return s
+
+
+def pimc_hmc(ctx: Context, spec, batch: PackedBatch, *, seed: int, k0: int, eps: float, L_steps: int,
+             minv: Sequence[float], n_proposals: int, stats: Optional[HmcStats] = None, stream=None):
+    """Hybrid Monte Carlo proposals for every window of a packed batch."""
+    m = model_struct(spec)
+    b = batch.struct()
+    mv = (C.c_double * 11)(*[float(v) for v in minv])
+    st = C.byref(stats.struct()) if stats is not None else None
+    L.check(ctx.lib.pimc_hmc(ctx.h, C.byref(m), C.byref(b), int(seed), int(k0), float(eps), int(L_steps), mv,
+                             int(n_proposals), st, _stream(stream)), "pimc_hmc")

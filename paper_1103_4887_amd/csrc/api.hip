@@ -8,6 +8,7 @@
 #include <numeric>
 #include <vector>
 
+#include "hmc.hpp"
 #include "kernels.hpp"
 #include "pimc.h"
 
@@ -27,6 +28,24 @@ struct pimc_ctx {
   double* wpart = nullptr;
   uint32_t* wsync = nullptr;
   uint64_t spin_ticks = 0;
+  // HMC workspace (grow-only)
+  size_t hmc_sites = 0, hmc_blocks = 0, hmc_B = 0, hmc_tsize = 0;
+  void* hQ1 = nullptr;
+  void* hR0 = nullptr;
+  void* hR1 = nullptr;
+  void* hX0 = nullptr;
+  double* hpart = nullptr;
+  double* hp0 = nullptr;
+  double* hpbuf = nullptr;
+  double* hrpbuf = nullptr;
+  double* hH0 = nullptr;
+  double* hdH = nullptr;
+  uint32_t* hout = nullptr;
+  uint8_t* hacc = nullptr;
+  int64_t* hoff = nullptr;
+  int32_t* hbmap = nullptr;
+  int32_t* hbfirst = nullptr;
+  uint64_t* hk = nullptr;
 };
 
 namespace {
@@ -232,6 +251,10 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (ctx->hflag) (void)hipFree(ctx->hflag);
   if (ctx->wpart) (void)hipFree(ctx->wpart);
   if (ctx->wsync) (void)hipFree(ctx->wsync);
+  void* hbufs[] = {ctx->hQ1, ctx->hR0, ctx->hR1, ctx->hX0, ctx->hpart, ctx->hp0, ctx->hpbuf, ctx->hrpbuf,
+                   ctx->hH0, ctx->hdH, ctx->hout, ctx->hacc, ctx->hoff, ctx->hbmap, ctx->hbfirst, ctx->hk};
+  for (void* q : hbufs)
+    if (q) (void)hipFree(q);
   delete ctx;
 }
 
@@ -441,3 +464,107 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
 }
 
 }  // extern "C"
+
+namespace {
+
+int hmc_workspace(pimc_ctx* c, size_t S, size_t nb, size_t B, size_t ts) {
+  if (S <= c->hmc_sites && nb <= c->hmc_blocks && B <= c->hmc_B && ts <= c->hmc_tsize && c->hk) return PIMC_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
+  void** bufs[] = {&c->hQ1, &c->hR0, &c->hR1, &c->hX0, (void**)&c->hpart, (void**)&c->hp0, (void**)&c->hpbuf,
+                   (void**)&c->hrpbuf, (void**)&c->hH0, (void**)&c->hdH, (void**)&c->hout, (void**)&c->hacc,
+                   (void**)&c->hoff, (void**)&c->hbmap, (void**)&c->hbfirst, (void**)&c->hk};
+  for (void** q : bufs) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  S = std::max(S, c->hmc_sites);
+  nb = std::max(nb, c->hmc_blocks);
+  B = std::max(B, c->hmc_B);
+  ts = std::max(ts, c->hmc_tsize);
+  const size_t sz[] = {S * 4 * ts, S * 4 * ts, S * 4 * ts, S * 4 * ts, 2 * nb * 16 * 8, B * 7 * 8, 2 * B * 7 * 8,
+                       2 * B * 7 * 8, B * 8, B * 8, B * 4, B, (B + 1) * 8, nb * 4, (B + 1) * 4, 8};
+  for (size_t i = 0; i < sizeof(sz) / sizeof(sz[0]); ++i)
+    if (hipMalloc(bufs[i], sz[i]) != hipSuccess) return PIMC_ERR_NOMEM;
+  c->hmc_sites = S;
+  c->hmc_blocks = nb;
+  c->hmc_B = B;
+  c->hmc_tsize = ts;
+  return PIMC_OK;
+}
+
+}  // namespace
+
+extern "C" int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, uint64_t seed, uint64_t k0,
+                        double eps, int32_t L, const double* minv, int64_t n_proposals, const pimc_hmc_stats* stats,
+                        void* stream) {
+  if (!ctx || !b || !minv || !b->offsets || !b->X || !b->p || !b->y || !b->I || !b->chain) return PIMC_ERR_ARG;
+  if (b->B < 1 || (b->prec != PIMC_FP64 && b->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  if (!(eps > 0.0) || L < 1 || n_proposals < 0) return PIMC_ERR_ARG;
+  for (int i = 0; i < 11; ++i)
+    if (!(minv[i] > 0.0)) return PIMC_ERR_ARG;
+  if (n_proposals == 0) return PIMC_OK;
+  const int B = b->B;
+  if (b->offsets[0] != 0) return PIMC_ERR_ARG;
+  std::vector<int32_t> bfirst(B + 1), bmap;
+  for (int i = 0; i < B; ++i) {
+    const int64_t Mi = b->offsets[i + 1] - b->offsets[i] - 1;
+    if (Mi < 1 || Mi >= (1ll << 30)) return PIMC_ERR_ARG;
+    bfirst[i] = (int32_t)bmap.size();
+    const int64_t nbk = (Mi + 1 + pimc::HMC_BLOCK - 1) / pimc::HMC_BLOCK;
+    for (int64_t q = 0; q < nbk; ++q) bmap.push_back(i);
+  }
+  bfirst[B] = (int32_t)bmap.size();
+  pimc::HmcArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  const bool fp64 = b->prec == PIMC_FP64;
+  const size_t S = (size_t)b->offsets[B];
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  if ((r = hmc_workspace(ctx, S, bmap.size(), (size_t)B, fp64 ? 8 : 4))) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->hoff, b->offsets, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s))))
+    return r;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->hbmap, bmap.data(), bmap.size() * 4, hipMemcpyHostToDevice, s)))) return r;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->hbfirst, bfirst.data(), (B + 1) * 4, hipMemcpyHostToDevice, s)))) return r;
+  if ((r = hip_ok(hipMemcpyAsync(ctx->hk, &k0, sizeof(k0), hipMemcpyHostToDevice, s)))) return r;
+  if ((r = hip_ok(hipStreamSynchronize(s)))) return r;   // host vectors die at return
+  a.cf.init(a.m);
+  a.cd.init(a.m);
+  a.B = B;
+  a.nblocks = (int32_t)bmap.size();
+  a.offsets = ctx->hoff;
+  a.bmap = ctx->hbmap;
+  a.bfirst = ctx->hbfirst;
+  a.X = b->X;
+  a.p = b->p;
+  a.y = b->y;
+  a.I = b->I;
+  a.chain = b->chain;
+  a.seed = seed;
+  a.kptr = ctx->hk;
+  a.k_first = k0;
+  a.eps = eps;
+  for (int i = 0; i < 11; ++i) a.minv[i] = minv[i];
+  a.Q1 = ctx->hQ1;
+  a.R0 = ctx->hR0;
+  a.R1 = ctx->hR1;
+  a.X0 = ctx->hX0;
+  a.p0 = ctx->hp0;
+  a.pbuf = ctx->hpbuf;
+  a.rpbuf = ctx->hrpbuf;
+  a.part = ctx->hpart;
+  a.H0 = ctx->hH0;
+  a.outside = ctx->hout;
+  a.accepted = ctx->hacc;
+  a.dH = ctx->hdH;
+  if (stats) {
+    a.acc = stats->acc;
+    a.ptrace = stats->ptrace;
+    a.dHtrace = stats->dH;
+  }
+  a.ntrace = n_proposals;
+  for (int64_t q = 0; q < n_proposals; ++q)
+    if ((r = pimc::launch_hmc_proposal(a, fp64, L, s))) return r;
+  return PIMC_OK;
+}

@@ -1,0 +1,434 @@
+// Hybrid Monte Carlo proposals on the path action, for many chains at once.
+//
+// The paper names Hybrid Monte Carlo among the samplers of exp(-A) (Section 3)
+// and derivative-based proposals as a way to converge in fewer iterations
+// (Section 3.1).  One proposal for every chain of a packed batch:
+//
+//   r ~ N(0, 1/minv) per site component and sampled parameter
+//   H0 = A(q0) + 1/2 sum r^2 minv                          (FP64)
+//   r(1/2) = r0 - e/2 g(q0)
+//   for s = 1..L:  q(s) = q(s-1) + e minv r(s-1/2);  g(s) = dA/dq at q(s)
+//                  r(s+1/2) = r(s-1/2) - e g(s)  (the last step kicks e/2)
+//   H1 = A(qL) + 1/2 sum rL^2 minv;  accept iff log u < -(H1 - H0)
+//   and no position left the box at any step.
+//
+// One kernel per leapfrog step over all chains' sites (blocks of 256 sites
+// of one chain, plus one halo site on each side whose drift is recomputed
+// locally), positions and momenta double-buffered by step parity, FP64
+// partials per block.  Every kernel of the parameter part reduces the
+// previous kernel's partials of its chain in block order, so all blocks of a
+// chain hold identical parameter values without any inter-block wait.  The
+// proposal index is read from device memory, so the launch sequence of one
+// proposal is fixed and can be captured and replayed.
+#include "device.hpp"
+#include "hmc.hpp"
+
+namespace pimc {
+
+namespace {
+
+constexpr int HB = HMC_BLOCK;  // sites per block = threads per block
+constexpr int NPART = 10;      // gp[7], A_o, A_d, K
+
+__device__ __forceinline__ double block_sum_d(double v, double* lds, int t) {
+  // 256 threads = 4 waves: DPP-free xor butterfly, then 4 wave sums in order
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((t & 63) == 0) lds[t >> 6] = v;
+  __syncthreads();
+  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+template <typename T>
+struct HmcJ {  // Jacobian rows of the HH field
+  T VV, Vg[3], gV[3], gg[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void hh_jac(const Consts<T>& C, const T (&x)[4], HmcJ<T>& J) {
+  const T V = x[0], m = x[1], hh = x[2], n = x[3];
+  const T m2 = m * m, m3 = m2 * m, n2 = n * n, n3 = n2 * n, n4 = n2 * n2;
+  J.VV = -(C.p[1] * m3 * hh + C.p[3] * n4 + C.p[5]);
+  J.Vg[0] = (T)3 * C.p[1] * m2 * hh * (C.p[2] - V);
+  J.Vg[1] = C.p[1] * m3 * (C.p[2] - V);
+  J.Vg[2] = (T)4 * C.p[3] * n3 * (C.p[4] - V);
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const T t = Math<T>::tanh((V - C.Va[g]) * C.inv_dVa[g]);
+    const T sech2 = (T)1 - t * t;
+    const T ainf = (T)0.5 + (T)0.5 * t;
+    const T tau = C.tau0[g] + C.tau1[g] * sech2;
+    const T itau = Math<T>::rcp(tau);
+    const T dt_dV = sech2 * C.inv_dVa[g];
+    J.gV[g] = (T)0.5 * dt_dV * itau - (ainf - x[1 + g]) * ((T)-2 * C.tau1[g] * t * dt_dV) * itau * itau;
+    J.gg[g] = -itau;
+  }
+}
+
+// dF_V/dp at a site, in FP64 from the site's state
+__device__ __forceinline__ void dFVdp(const double* p, double V, double m, double h, double n, double I,
+                                      double (&d)[7]) {
+  const double m3h = m * m * m * h, n4 = n * n * n * n;
+  d[0] = I;
+  d[1] = m3h * (p[2] - V);
+  d[2] = p[1] * m3h;
+  d[3] = n4 * (p[4] - V);
+  d[4] = p[3] * n4;
+  d[5] = p[6] - V;
+  d[6] = p[5];
+}
+
+// Parameter state of chain `ch` at leapfrog kernel s (identical in every
+// block of the chain): p(s), and the momentum rp(s-1/2) that moved it there.
+__device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, bool last_step, double (&ps)[7],
+                                             double (&rps)[7], double (&gp_prev)[7], double* red) {
+  (void)last_step;
+  const int b0 = a.bfirst[ch], b1 = a.bfirst[ch + 1];
+  const double* part = a.part + (int64_t)((s - 1) & 1) * a.nblocks * 16;
+  // fixed-order reduction of the previous kernel's partials of this chain
+  const int t = threadIdx.x;
+  if (t < 7) {
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) acc += part[(int64_t)b * 16 + t];
+    red[t] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < 7; ++l) gp_prev[l] = red[l];
+  const double c = s == 1 ? 0.5 : 1.0;
+  const double* rp_in = a.rpbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
+  const double* p_in = s == 1 ? a.p + (int64_t)ch * 7 : a.pbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
+#pragma unroll
+  for (int l = 0; l < 7; ++l) {
+    const bool on = (a.m.p_mask >> l) & 1;
+    rps[l] = on ? rp_in[l] - c * a.eps * gp_prev[l] : 0.0;
+    ps[l] = on ? p_in[l] + a.eps * a.minv[4 + l] * rps[l] : p_in[l];
+  }
+}
+
+}  // namespace
+
+// MODE 0: initial kernel (momenta, g(q0), H0 partials);
+// MODE 1: interior leapfrog step; MODE 2: last step (half kick, H1 partials).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
+  __shared__ T lq[HB + 2][4];
+  __shared__ T lF[HB + 2][4];
+  __shared__ T lI[HB + 2];
+  __shared__ double red[16];
+  __shared__ double lsum[4];
+  const int t = threadIdx.x;
+  const int b = blockIdx.x;
+  const int ch = a.bmap[b];
+  const int64_t base = a.offsets[ch];
+  const int M = (int)(a.offsets[ch + 1] - base - 1);
+  const int site0 = (b - a.bfirst[ch]) * HB;
+  const uint64_t k = *a.kptr;
+  const Key key = make_key(a.seed, a.chain[ch]);
+
+  Consts<T> C;
+  if constexpr (sizeof(T) == 4)
+    C = a.cf;
+  else
+    C = a.cd;
+
+  // ---- parameters at this step -------------------------------------------
+  double ps[7], rps[7], gpp[7];
+  if (MODE == 0) {
+#pragma unroll
+    for (int l = 0; l < 7; ++l) ps[l] = a.p[(int64_t)ch * 7 + l];
+  } else {
+    chain_params(a, ch, s, MODE == 2, ps, rps, gpp, red);
+    bool out = false;
+#pragma unroll
+    for (int l = 0; l < 7; ++l)
+      if ((a.m.p_mask >> l) & 1) out = out || !(ps[l] >= a.m.p_lo[l] && ps[l] <= a.m.p_hi[l]);
+    if (b == a.bfirst[ch] && t == 0) {
+      double* rp_out = a.rpbuf + (int64_t)(s & 1) * a.B * 7 + (int64_t)ch * 7;
+      double* p_out = a.pbuf + (int64_t)(s & 1) * a.B * 7 + (int64_t)ch * 7;
+#pragma unroll
+      for (int l = 0; l < 7; ++l) {
+        rp_out[l] = rps[l];
+        p_out[l] = ps[l];
+      }
+      if (out) atomicOr(&a.outside[ch], 1u);
+      if (s == 1) {
+        // H0 from the initial kernel's partials: A(q0) + K(r0) + K(rp0)
+        const double* part0 = a.part;  // parity 0
+        double Ao = 0.0, Ad = 0.0, Ks = 0.0;
+        for (int bb = a.bfirst[ch]; bb < a.bfirst[ch + 1]; ++bb) {
+          Ao += part0[(int64_t)bb * 16 + 7];
+          Ad += part0[(int64_t)bb * 16 + 8];
+          Ks += part0[(int64_t)bb * 16 + 9];
+        }
+        const double* rp0 = a.rpbuf + (int64_t)ch * 7;  // parity 0 holds rp0
+        double Kp = 0.0;
+#pragma unroll
+        for (int l = 0; l < 7; ++l) Kp += 0.5 * rp0[l] * rp0[l] * a.minv[4 + l];
+        a.H0[ch] = Ao + a.m.beta * Ad + Ks + Kp;
+      }
+    }
+  }
+  C.set_p(ps);
+
+  // ---- positions of the block's sites and the two halo sites -------------
+  // lq[j] holds site n = site0 - 1 + j
+  const T* Qin = (const T*)(MODE == 0 ? a.X : (((s - 1) & 1) ? a.Q1 : a.X)) + base * 4;
+  const T* Rin = (const T*)(((s - 1) & 1) ? a.R1 : a.R0) + base * 4;   // r(s-1/2)
+  const T* Ip = (const T*)a.I + base;
+  const T e = (T)a.eps;
+  T minv_s[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) minv_s[c] = (T)a.minv[c];
+  for (int j = t; j < HB + 2; j += HB) {
+    const int n = site0 - 1 + j;
+    if (n >= 0 && n <= M) {
+      T q[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        q[c] = Qin[(int64_t)n * 4 + c];
+        if (MODE != 0) q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
+        lq[j][c] = q[c];
+      }
+      const T I = Ip[n];
+      lI[j] = I;
+      T F[4];
+      hh_F(C, q, I, F);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) lF[j][c] = F[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- own site: gradient, kick, partials ---------------------------------
+  const int n = site0 + t;
+  const int j = t + 1;
+  double part[NPART];
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) part[i] = 0.0;
+  if (n <= M) {
+    T x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = lq[j][c];
+    bool out = false;
+    if (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) out = out || !(x[c] >= C.lo[c] && x[c] <= C.hi[c]);
+      if (out) atomicOr(&a.outside[ch], 1u);
+    }
+    const T h = C.h;
+    const T beta = (T)a.m.beta;
+    T vl[4] = {0, 0, 0, 0}, vr[4] = {0, 0, 0, 0}, el[4] = {0, 0, 0, 0};
+    if (n >= 1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        el[c] = (x[c] - lq[j - 1][c]) - h * (lF[j][c] + lF[j - 1][c]);
+        vl[c] = beta * (T)a.m.Rd[c] * el[c];
+      }
+    }
+    if (n + 1 <= M) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        vr[c] = beta * (T)a.m.Rd[c] * ((lq[j + 1][c] - x[c]) - h * (lF[j + 1][c] + lF[j][c]));
+    }
+    HmcJ<T> J;
+    hh_jac(C, x, J);
+    T u[4], w[4], g[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      u[c] = vl[c] - vr[c];
+      w[c] = vl[c] + vr[c];
+    }
+    g[0] = u[0] - h * (J.VV * w[0] + J.gV[0] * w[1] + J.gV[1] * w[2] + J.gV[2] * w[3]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[1 + q] = u[1 + q] - h * (J.Vg[q] * w[0] + J.gg[q] * w[1 + q]);
+    const T* Yp = (const T*)a.y + base;
+    if (n >= 1) g[0] -= (T)a.m.Ro * (Yp[n] - x[0]);
+
+    // momenta: drawn (MODE 0) or r(s-1/2); kick; kinetic energy partial
+    T r[4];
+    if (MODE == 0) {
+      const U4 blk = draw(key, (uint32_t)n, k, TAG_MOM);
+      T z[4];
+      Math<T>::box_muller(blk.x, blk.y, z[0], z[1]);
+      Math<T>::box_muller(blk.z, blk.w, z[2], z[3]);
+      double kin = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        r[c] = z[c] / (T)sqrt(a.minv[c]);
+        kin += 0.5 * (double)r[c] * (double)r[c] * a.minv[c];
+      }
+      part[9] = kin;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = Rin[(int64_t)n * 4 + c];
+    }
+    const T kick = MODE == 1 ? e : e * (T)0.5;
+    T rn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rn[c] = r[c] - kick * g[c];
+    T* Rout = (T*)((s & 1) ? a.R1 : a.R0) + base * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Rout[(int64_t)n * 4 + c] = rn[c];
+    if (MODE != 0) {
+      T* Qout = (T*)((s & 1) ? a.Q1 : a.X) + base * 4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Qout[(int64_t)n * 4 + c] = x[c];
+    } else {
+      T* X0 = (T*)a.X0 + base * 4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) X0[(int64_t)n * 4 + c] = x[c];
+    }
+    if (MODE == 2) {
+      double kin = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) kin += 0.5 * (double)rn[c] * (double)rn[c] * a.minv[c];
+      part[9] = kin;
+    }
+    // action terms (initial and last kernels) and dA/dp of link n
+    if (n >= 1) {
+      if (MODE != 1) {
+        const double d = (double)Yp[n] - (double)x[0];
+        part[7] = 0.5 * a.m.Ro * d * d;
+        double s2 = 0.0;
+        // FP64 model error of link n for the Hamiltonian
+        double x1[4], x0[4], F1[4], F0[4];
+        Consts<double> CD = a.cd;
+        CD.set_p(ps);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          x1[c] = (double)x[c];
+          x0[c] = (double)lq[j - 1][c];
+        }
+        hh_F(CD, x1, (double)lI[j], F1);
+        hh_F(CD, x0, (double)lI[j - 1], F0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double ee = (x1[c] - x0[c]) - CD.h * (F1[c] + F0[c]);
+          s2 += a.m.Rd[c] * ee * ee;
+        }
+        part[8] = 0.5 * s2;
+      }
+      double d1[7], d0[7];
+      dFVdp(ps, (double)x[0], (double)x[1], (double)x[2], (double)x[3], (double)lI[j], d1);
+      dFVdp(ps, (double)lq[j - 1][0], (double)lq[j - 1][1], (double)lq[j - 1][2], (double)lq[j - 1][3],
+            (double)lI[j - 1], d0);
+      const double f = -0.5 * a.m.dt * (double)vl[0];
+#pragma unroll
+      for (int l = 0; l < 7; ++l) part[l] = f * (d1[l] + d0[l]);
+    }
+  }
+  // ---- block partials -------------------------------------------------------
+  double* pout = a.part + (int64_t)(s & 1) * a.nblocks * 16 + (int64_t)b * 16;
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) {
+    const double v = block_sum_d(part[i], lsum, t);
+    if (t == 0) pout[i] = v;
+  }
+  if (MODE == 0 && b == a.bfirst[ch] && t == 0) {
+    // parameter momenta and backups, chain-level (one block per chain)
+    const U4 q0 = draw(key, 0u, k, TAG_PMOM, 0);
+    const U4 q1 = draw(key, 0u, k, TAG_PMOM, 1);
+    double z[8];
+    Math<double>::box_muller(q0.x, q0.y, z[0], z[1]);
+    Math<double>::box_muller(q0.z, q0.w, z[2], z[3]);
+    Math<double>::box_muller(q1.x, q1.y, z[4], z[5]);
+    Math<double>::box_muller(q1.z, q1.w, z[6], z[7]);
+    double* rp0 = a.rpbuf + (int64_t)ch * 7;   // parity 0
+#pragma unroll
+    for (int l = 0; l < 7; ++l) {
+      const bool on = (a.m.p_mask >> l) & 1;
+      rp0[l] = on ? z[l] / sqrt(a.minv[4 + l]) : 0.0;
+      a.p0[(int64_t)ch * 7 + l] = ps[l];
+    }
+    a.outside[ch] = 0u;
+  }
+}
+
+// One block per chain: H1, decision, parameters, counters.
+__global__ void hmc_finish_kernel(HmcArgs a, int L) {
+  const int ch = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const uint64_t k = *a.kptr;
+  const Key key = make_key(a.seed, a.chain[ch]);
+  const double* part = a.part + (int64_t)(L & 1) * a.nblocks * 16;
+  double gp[7] = {0, 0, 0, 0, 0, 0, 0}, Ao = 0.0, Ad = 0.0, Ks = 0.0;
+  for (int b = a.bfirst[ch]; b < a.bfirst[ch + 1]; ++b) {
+#pragma unroll
+    for (int l = 0; l < 7; ++l) gp[l] += part[(int64_t)b * 16 + l];
+    Ao += part[(int64_t)b * 16 + 7];
+    Ad += part[(int64_t)b * 16 + 8];
+    Ks += part[(int64_t)b * 16 + 9];
+  }
+  const double* rpL = a.rpbuf + (int64_t)(L & 1) * a.B * 7 + (int64_t)ch * 7;   // rp(L-1/2)
+  const double* pL = a.pbuf + (int64_t)(L & 1) * a.B * 7 + (int64_t)ch * 7;
+  double Kp = 0.0;
+#pragma unroll
+  for (int l = 0; l < 7; ++l) {
+    const bool on = (a.m.p_mask >> l) & 1;
+    const double r = on ? rpL[l] - 0.5 * a.eps * gp[l] : 0.0;
+    Kp += 0.5 * r * r * a.minv[4 + l];
+  }
+  const double H1 = Ao + a.m.beta * Ad + Ks + Kp;
+  const double dH = H1 - a.H0[ch];
+  const double u = u01_d(draw(key, 0u, k, TAG_HACC).x);
+  const bool ok = a.outside[ch] == 0u && __builtin_isfinite(dH) && ::log(u) < -dH;
+  a.accepted[ch] = ok ? 1 : 0;
+  a.dH[ch] = dH;
+#pragma unroll
+  for (int l = 0; l < 7; ++l) a.p[(int64_t)ch * 7 + l] = ok ? pL[l] : a.p0[(int64_t)ch * 7 + l];
+  if (a.acc) {
+    a.acc[(int64_t)ch * PIMC_NACC + 0] += ok ? 1 : 0;
+    if (!__builtin_isfinite(dH)) a.acc[(int64_t)ch * PIMC_NACC + PIMC_ACC_NONFINITE] += 1;
+    if (a.outside[ch]) a.acc[(int64_t)ch * PIMC_NACC + 1] += 1;
+  }
+  if (a.ptrace) {
+    const int64_t it = (int64_t)(k - a.k_first);
+#pragma unroll
+    for (int l = 0; l < 7; ++l) a.ptrace[((int64_t)ch * a.ntrace + it) * 7 + l] = a.p[(int64_t)ch * 7 + l];
+  }
+  if (a.dHtrace) a.dHtrace[(int64_t)ch * a.ntrace + (int64_t)(k - a.k_first)] = dH;
+}
+
+// Final positions: the end of the trajectory if accepted, else the start.
+template <typename T>
+__global__ void hmc_restore_kernel(HmcArgs a, int L) {
+  const int b = blockIdx.x;
+  const int ch = a.bmap[b];
+  const int64_t base = a.offsets[ch];
+  const int M = (int)(a.offsets[ch + 1] - base - 1);
+  const int n = (b - a.bfirst[ch]) * HB + threadIdx.x;
+  if (n > M) return;
+  const bool ok = a.accepted[ch] != 0;
+  const T* src = (const T*)(ok ? ((L & 1) ? a.Q1 : a.X) : a.X0) + (base + n) * 4;
+  T* X = (T*)a.X + (base + n) * 4;
+  if (src != X) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) X[c] = src[c];
+  }
+}
+
+__global__ void hmc_advance_kernel(uint64_t* kptr) { *kptr += 1; }
+
+int launch_hmc_proposal(const HmcArgs& a, bool fp64, int L, hipStream_t s) {
+  const dim3 gb(a.nblocks), tb(HB);
+  if (fp64) {
+    hipLaunchKernelGGL((hmc_step_kernel<double, 0>), gb, tb, 0, s, a, 0);
+    for (int st = 1; st < L; ++st) hipLaunchKernelGGL((hmc_step_kernel<double, 1>), gb, tb, 0, s, a, st);
+    hipLaunchKernelGGL((hmc_step_kernel<double, 2>), gb, tb, 0, s, a, L);
+  } else {
+    hipLaunchKernelGGL((hmc_step_kernel<float, 0>), gb, tb, 0, s, a, 0);
+    for (int st = 1; st < L; ++st) hipLaunchKernelGGL((hmc_step_kernel<float, 1>), gb, tb, 0, s, a, st);
+    hipLaunchKernelGGL((hmc_step_kernel<float, 2>), gb, tb, 0, s, a, L);
+  }
+  hipLaunchKernelGGL(hmc_finish_kernel, dim3(a.B), dim3(64), 0, s, a, L);
+  if (fp64)
+    hipLaunchKernelGGL(hmc_restore_kernel<double>, gb, tb, 0, s, a, L);
+  else
+    hipLaunchKernelGGL(hmc_restore_kernel<float>, gb, tb, 0, s, a, L);
+  hipLaunchKernelGGL(hmc_advance_kernel, dim3(1), dim3(1), 0, s, a.kptr);
+  return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
+}
+
+}  // namespace pimc

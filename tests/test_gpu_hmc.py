@@ -1,0 +1,119 @@
+"""HMC proposals of the HIP library against the oracle's leapfrog/HMC.
+
+FP64: the decision of every chain equals the oracle's wherever
+|dH + log u| > 1e-6, dH agrees to 1e-8 relative (plus 1e-9 absolute), final
+positions and parameters to 1e-10.  FP32 trajectories carry FP32 rounding:
+dH agrees to 5e-3 absolute, decisions where the margin exceeds 1e-2.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hmc as OH
+from oracle import philox as ph
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1103_4887_amd")
+
+pytestmark = pytest.mark.gpu
+
+MINV = np.array([0.3, 1e-5, 1e-5, 1e-5] + [1.0] * 7)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _chains(Ms, mask=0x7F, seed0=300):
+    probs = []
+    for i, M in enumerate(Ms):
+        spec = W.ModelSpec(p_mask=mask)
+        pr = W.make_hh_problem(M, 0.02, seed0 + i, model=spec, require_spike=False, init="truth")
+        probs.append(pr)
+    return probs
+
+
+def _minv_p(probs):
+    return (1e-3 * np.abs(np.asarray(W.P_STAR))) ** 2
+
+
+def _oracle(probs, chains, seed, k0, eps, L, minv, n):
+    outs = []
+    for pr, chn in zip(probs, chains):
+        X, p = pr.X0.copy(), pr.p0.copy()
+        dHs, oks, us = [], [], []
+        for k in range(k0, k0 + n):
+            X, p, ok, dH = OH.hmc_proposal(pr.model, X, p, pr.y, pr.I, seed=seed, chain=chn, k=k, e=eps, L=L,
+                                           minv_state=minv[:4], minv_param=minv[4:])
+            dHs.append(dH)
+            oks.append(ok)
+            us.append(float(ph.uniform_open(ph.draw(seed, chn, 0, k, ph.TAG_HACC)[0, 0])))
+        outs.append((X, p, np.array(dHs), np.array(oks), np.array(us)))
+    return outs
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_hmc_fp64_matches_oracle(ctx, n):
+    probs = _chains([37, 300, 64])
+    minv = MINV.copy()
+    minv[4:] = _minv_p(probs)
+    chains = [3, 8, 11]
+    eps, L, seed, k0 = 0.004, 6, 77, 10
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], chains, "fp64")
+    st = P.HmcStats.allocate(len(probs), n)
+    print(f"hmc fp64 n={n}", flush=True)
+    P.pimc_hmc(ctx, probs[0].model, batch, seed=seed, k0=k0, eps=eps, L_steps=L, minv=minv, n_proposals=n, stats=st)
+    assert ctx.sync() == 0
+    ref = _oracle(probs, chains, seed, k0, eps, L, minv, n)
+    gdH = st.dH.cpu().numpy()
+    acc = st.acc.cpu().numpy()
+    for i, (Xo, po, dHo, oko, uo) in enumerate(ref):
+        inside = np.isfinite(dHo)          # the oracle reports NaN for trajectories that left the box
+        np.testing.assert_allclose(gdH[i][inside], dHo[inside], rtol=1e-8, atol=1e-9)
+        assert acc[i, 1] == (~inside).sum()
+        safe = np.abs(dHo[inside] + np.log(uo[inside])) > 1e-6
+        assert safe.all()   # this case is chosen away from ties
+        assert acc[i, 0] == oko.sum()
+        Xb, pb, _, _ = batch.window(i)
+        np.testing.assert_allclose(Xb.cpu().numpy(), Xo, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(pb.cpu().numpy(), po, rtol=1e-12)
+    assert 0 < acc[:, 0].sum()
+
+
+def test_hmc_fp32_close_to_oracle(ctx):
+    probs = _chains([300, 129])
+    minv = MINV.copy()
+    minv[4:] = _minv_p(probs)
+    chains = [1, 2]
+    eps, L, seed, k0 = 0.004, 6, 5, 0
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], chains, "fp32")
+    st = P.HmcStats.allocate(len(probs), 1)
+    P.pimc_hmc(ctx, probs[0].model, batch, seed=seed, k0=k0, eps=eps, L_steps=L, minv=minv, n_proposals=1, stats=st)
+    assert ctx.sync() == 0
+    ref = _oracle(probs, chains, seed, k0, eps, L, minv, 1)
+    gdH = st.dH.cpu().numpy()[:, 0]
+    for i, (Xo, po, dHo, oko, uo) in enumerate(ref):
+        assert abs(gdH[i] - dHo[0]) < 5e-3 + 1e-3 * abs(dHo[0])
+        if abs(dHo[0] + np.log(uo[0])) > 1e-2:
+            assert st.acc.cpu().numpy()[i, 0] == int(oko[0])
+
+
+def test_hmc_leaving_box_rejects(ctx):
+    probs = _chains([64])
+    minv = MINV.copy()
+    minv[4:] = _minv_p(probs)
+    batch = P.PackedBatch.pack([probs[0].X0], [probs[0].p0], [probs[0].y], [probs[0].I], [0], "fp32")
+    X_before = batch.X.clone()
+    p_before = batch.p.clone()
+    st = P.HmcStats.allocate(1, 2)
+    P.pimc_hmc(ctx, probs[0].model, batch, seed=1, k0=0, eps=5.0, L_steps=3, minv=minv, n_proposals=2, stats=st)
+    assert ctx.sync() == 0
+    acc = st.acc.cpu().numpy()[0]
+    assert acc[0] == 0 and acc[1] == 2
+    assert torch.equal(batch.X, X_before) and torch.equal(batch.p, p_before)

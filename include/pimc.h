@@ -236,7 +236,10 @@ typedef struct {
  *   (u at the HACC address) and no position left the box at any step.
  * Proposal indices are k0 .. k0 + n_proposals - 1.  minv: HOST FP64 [11],
  * inverse masses of (V, m, h, n) then p1..p7 (unsampled parameters never
- * move).  eps > 0, L >= 1.  Positions and parameters are updated in place. */
+ * move).  eps > 0, L >= 1.  Positions and parameters are updated in place.
+ * With n_proposals > 1 the launches of one proposal are captured into a HIP
+ * graph and replayed; the call then waits for the stream before returning
+ * (environment PIMC_NO_GRAPHS=1 launches kernel by kernel instead). */
 int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* batch, uint64_t seed, uint64_t k0,
              double eps, int32_t L, const double* minv, int64_t n_proposals, const pimc_hmc_stats* stats,
              void* stream);

@@ -22,6 +22,8 @@ struct pimc_ctx {
   size_t batch_cap = 0;           // in windows
   int tile_K = 0;                 // 0 = automatic choice of sites per thread
   int tiles = 0;                  // 0 = automatic number of time tiles per window
+  bool no_graphs = false;         // launch HMC proposals one kernel at a time
+  hipStream_t cap = nullptr;      // private stream that only records graphs (never runs work)
   // cross-tile workspace of one window split over up to MAX_TILES workgroups
   void* halo = nullptr;
   uint32_t* hflag = nullptr;
@@ -224,6 +226,7 @@ int pimc_ctx_create(pimc_ctx** out, int device) {
     return PIMC_ERR_HIP;
   }
   if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
+  if (const char* e = std::getenv("PIMC_NO_GRAPHS")) c->no_graphs = std::atoi(e) != 0;
   bool ok = hipMalloc(&c->halo, (size_t)MAX_TILES * 16 * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->hflag, (size_t)MAX_TILES * 2 * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(&c->wpart, (size_t)2 * MAX_TILES * 35 * sizeof(double)) == hipSuccess &&
@@ -243,6 +246,7 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->err) (void)hipFree(ctx->err);
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->offsets) (void)hipFree(ctx->offsets);
@@ -564,7 +568,34 @@ extern "C" int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch
     a.dHtrace = stats->dH;
   }
   a.ntrace = n_proposals;
-  for (int64_t q = 0; q < n_proposals; ++q)
-    if ((r = pimc::launch_hmc_proposal(a, fp64, L, s))) return r;
-  return PIMC_OK;
+  if (n_proposals == 1 || ctx->no_graphs) {
+    for (int64_t q = 0; q < n_proposals; ++q)
+      if ((r = pimc::launch_hmc_proposal(a, fp64, L, s))) return r;
+    return PIMC_OK;
+  }
+  // The L + 4 launches of one proposal take fixed arguments (the proposal
+  // index is in device memory), so they are captured once and replayed on
+  // the caller's stream.  Capture happens on a private stream because the
+  // caller's may be the legacy default stream, which cannot be captured;
+  // recording runs nothing, so that stream needs no ordering with `s`.
+  if (!ctx->cap && (r = hip_ok(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)))) return r;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if ((r = hip_ok(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)))) return r;
+  const int lr = pimc::launch_hmc_proposal(a, fp64, L, ctx->cap);
+  const hipError_t ec = hipStreamEndCapture(ctx->cap, &g);
+  if (lr || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return lr ? lr : PIMC_ERR_HIP;
+  }
+  if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return PIMC_ERR_HIP;
+  }
+  for (int64_t q = 0; q < n_proposals && !r; ++q) r = hip_ok(hipGraphLaunch(ge, s));
+  // the executable graph may be destroyed once its launches are enqueued
+  const int r2 = hip_ok(hipStreamSynchronize(s));
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  return r ? r : r2;
 }

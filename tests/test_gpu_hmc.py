@@ -117,3 +117,36 @@ def test_hmc_leaving_box_rejects(ctx):
     acc = st.acc.cpu().numpy()[0]
     assert acc[0] == 0 and acc[1] == 2
     assert torch.equal(batch.X, X_before) and torch.equal(batch.p, p_before)
+
+
+def test_hmc_graph_replays_equal_eager(ctx):
+    """Proposals replayed from one captured graph equal kernel-by-kernel
+    proposals, including across two calls with eager work in between."""
+    probs = _chains([300, 64])
+    minv = MINV.copy()
+    minv[4:] = _minv_p(probs)
+    chains = [4, 9]
+
+    def batch():
+        return P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                                  [q.I for q in probs], chains, "fp32")
+
+    ga = batch()
+    sa1 = P.HmcStats.allocate(2, 3)
+    sa2 = P.HmcStats.allocate(2, 3)
+    P.pimc_hmc(ctx, probs[0].model, ga, seed=6, k0=0, eps=0.004, L_steps=5, minv=minv, n_proposals=3, stats=sa1)
+    junk = torch.randn(4096, device="cuda")
+    junk = (junk * junk).sum()
+    torch.cuda.synchronize()
+    P.pimc_hmc(ctx, probs[0].model, ga, seed=6, k0=3, eps=0.004, L_steps=5, minv=minv, n_proposals=3, stats=sa2)
+    assert ctx.sync() == 0
+    gb = batch()
+    dHb = []
+    for k in range(6):
+        sb = P.HmcStats.allocate(2, 1)
+        P.pimc_hmc(ctx, probs[0].model, gb, seed=6, k0=k, eps=0.004, L_steps=5, minv=minv, n_proposals=1, stats=sb)
+        assert ctx.sync() == 0
+        dHb.append(sb.dH.cpu().numpy()[:, 0])
+    assert torch.equal(ga.X, gb.X) and torch.equal(ga.p, gb.p)
+    dHa = np.concatenate([sa1.dH.cpu().numpy(), sa2.dH.cpu().numpy()], axis=1)
+    np.testing.assert_array_equal(dHa, np.stack(dHb, axis=1))

@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="sites per thread (0: autotune)")
     ap.add_argument("--tiles", type=int, default=-1, help="time tiles per window (-1: autotune)")
     ap.add_argument("--nskip", type=int, default=10, help="path moments every nskip-th sweep (N_skip)")
+    ap.add_argument("--cmp-seconds", type=float, default=20.0,
+                    help="wall budget of each sampler in the HMC vs plain sweep comparison (0: skip it)")
+    ap.add_argument("--cmp-chains", type=int, default=64)
     return ap.parse_args()
 
 
@@ -67,6 +70,104 @@ def cpu_baseline(prob, budget_s: float):
     return {"value": (prob.M + 1) * n / wall, "unit": "site-updates/s",
             "cores": max(1, round(cpu / wall)), "kind": "oracle",
             "sample": f"{n} sweeps of the same M={prob.M} window from its initial guess ({wall:.1f} s)"}
+
+
+def _post_stats(traces, mask):
+    """traces [chains][n][7] -> (sum over chains of per-chain ESS, pooled mean, MCSE) per sampled param."""
+    import numpy as np
+    from paper_1103_4887_amd import diag
+
+    ess = np.array([diag.ess_columns(t[:, mask]) for t in traces]).sum(axis=0)
+    pooled = traces[:, :, mask].reshape(-1, len(mask))
+    mean = pooled.mean(axis=0)
+    sd = pooled.std(axis=0)
+    return ess, mean, sd / np.sqrt(np.maximum(ess, 1.0))
+
+
+def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, L_steps: int = 20):
+    """Parameter ESS per second of HMC and of the plain sweep on one dataset.
+
+    Both samplers run `chains` chains from the same start (the true path and
+    parameters of the twin experiment, a draw from the posterior's bulk) for
+    the same wall budget, warm-up included; ESS is summed over chains on the
+    second half of each run.  HMC's warm-up is a pilot sweep run for the
+    diagonal masses plus dual-averaging of the step size to 0.7 acceptance.
+    """
+    import numpy as np
+    import torch
+
+    import paper_1103_4887_amd as P
+    from paper_1103_4887_amd import hmc as H
+
+    spec = prob.model
+    B = chains
+    mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+
+    def fresh():
+        return P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
+
+    # plain sweep: time a short run to size the budgeted one
+    bm = fresh()
+    t0 = time.perf_counter()
+    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=0, w=w, n_sweeps=50)
+    assert ctx.sync() == 0
+    t_probe = time.perf_counter()
+    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=50, w=w, n_sweeps=200)
+    assert ctx.sync() == 0
+    per_sweep = (time.perf_counter() - t_probe) / 200
+    n_m = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep))
+    stride = max(1, n_m // 20000)     # the trace is thinned on the host for the ESS estimate
+    dev = bm.X.device
+    sm = P.SweepStats(ptrace=torch.zeros((B, n_m, 7), dtype=torch.float64, device=dev),
+                      acc=torch.zeros((B, P._lib.PIMC_NACC), dtype=torch.int64, device=dev))
+    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=250, w=w, n_sweeps=n_m, stats=sm)
+    assert ctx.sync() == 0
+    wall_m = time.perf_counter() - t0
+    tr_m = sm.ptrace[:, n_m // 2::stride].cpu().numpy()
+    del sm.ptrace
+    ess_m, mean_m, mcse_m = _post_stats(tr_m, mask)
+    acc_m = sm.acc.cpu().numpy()
+
+    # HMC: pilot masses, step-size warm-up, then sampling in one graph-replayed call
+    bh = fresh()
+    t0 = time.perf_counter()
+    minv = H.pilot_minv(ctx, spec, bh, w, seed=prob.seed + 1, sweeps=2000)
+    tun = H.tune_eps(ctx, spec, bh, minv, seed=prob.seed + 2, L_steps=L_steps, warmup=200, eps0=0.01)
+    t_probe = time.perf_counter()
+    H.sample(ctx, spec, bh, tun, seed=prob.seed + 2, L_steps=L_steps, n=20, k0=200)
+    per_prop = (time.perf_counter() - t_probe) / 20
+    n_h = max(200, int((budget_s - (time.perf_counter() - t0)) / per_prop))
+    sh = H.sample(ctx, spec, bh, tun, seed=prob.seed + 2, L_steps=L_steps, n=n_h, k0=220)
+    wall_h = time.perf_counter() - t0
+    tr_h = sh.ptrace.cpu().numpy()
+    tr_h = tr_h[:, n_h // 2:]
+    ess_h, mean_h, mcse_h = _post_stats(tr_h, mask)
+    acc_h = sh.acc.cpu().numpy()
+
+    z = np.abs(mean_h - mean_m) / np.sqrt(mcse_h ** 2 + mcse_m ** 2)
+    return {
+        "dataset": f"HH M={prob.M}, dt={spec.dt} ms, all 7 params, FP32 sites + FP64 reductions",
+        "chains": B, "start": "true path and parameters", "budget_s": budget_s,
+        "sweep": {"sweeps": n_m, "trace_stride": stride, "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
+                  "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
+                  "param_ess_per_s": float(ess_m.min() / wall_m),
+                  "param_ess_per_s_median": float(np.median(ess_m) / wall_m),
+                  "param_ess": [float(v) for v in ess_m],
+                  "accept_sites": float(acc_m[:, :2].sum() / (B * (prob.M + 1) * n_m))},
+        "hmc": {"proposals": n_h, "leapfrog_steps": L_steps, "eps": tun.eps,
+                "warmup_accept": tun.warmup_accept, "wall_s": wall_h, "us_per_proposal": per_prop * 1e6,
+                "site_leapfrogs_per_s": B * (prob.M + 1) * L_steps * n_h / wall_h,
+                "accept": float(acc_h[:, 0].sum() / (B * n_h)),
+                "left_box": float(acc_h[:, 1].sum() / (B * n_h)),
+                "param_ess_per_s": float(ess_h.min() / wall_h),
+                "param_ess_per_s_median": float(np.median(ess_h) / wall_h),
+                "param_ess": [float(v) for v in ess_h]},
+        "hmc_over_sweep_param_ess_per_s": float((ess_h.min() / wall_h) / (ess_m.min() / wall_m)),
+        "equal_posterior_accuracy": {"max_z": float(z.max()), "within_3_mcse": bool((z <= 3.0).all()),
+                                     "mean_sweep": [float(v) for v in mean_m],
+                                     "mean_hmc": [float(v) for v in mean_h]},
+    }
 
 
 def main():
@@ -145,6 +246,9 @@ def main():
                      "kernel": "sweep_kernel", "slots_per_site_update": SLOTS_PER_SITE_UPDATE,
                      "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3},
     }
+    if args.cmp_seconds > 0:
+        out["hmc_vs_sweep"] = hmc_vs_sweep(ctx, W.config_problem(args.config, init="truth"), args.cmp_chains,
+                                           args.cmp_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]

@@ -8,8 +8,9 @@ libpimc.so (C ABI in include/pimc.h); this package only binds it.
 """
 
 from . import _lib
+from .autograd import PimcAction, action
 from .api import (Context, HmcStats, PackedBatch, SweepDebug, SweepStats, Window, model_struct, pimc_action,
                   pimc_grad, pimc_hmc, pimc_param_update, pimc_run_batch, pimc_sweep, widths_tensor)
 
-__all__ = ["Context", "HmcStats", "pimc_hmc", "PackedBatch", "SweepDebug", "SweepStats", "Window", "model_struct", "pimc_action",
+__all__ = ["PimcAction", "action", "Context", "HmcStats", "pimc_hmc", "PackedBatch", "SweepDebug", "SweepStats", "Window", "model_struct", "pimc_action",
            "pimc_grad", "pimc_param_update", "pimc_run_batch", "pimc_sweep", "widths_tensor", "_lib"]

@@ -24,7 +24,8 @@ struct pimc_ctx {
   int tiles = 0;                  // 0 = automatic number of time tiles per window
   bool no_graphs = false;         // launch HMC proposals one kernel at a time
   hipStream_t cap = nullptr;      // private stream that only records graphs (never runs work)
-  // cross-tile workspace of one window split over up to MAX_TILES workgroups
+  // cross-tile workspace: tile_cap tiles over group_cap windows (grow-only)
+  size_t tile_cap = 0, group_cap = 0;
   void* halo = nullptr;
   uint32_t* hflag = nullptr;
   double* wpart = nullptr;
@@ -121,6 +122,30 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
   if (hipMalloc(&ctx->offsets, (B + 1) * sizeof(int64_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   if (hipMalloc(&ctx->order, B * sizeof(int32_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   ctx->batch_cap = B;
+  return PIMC_OK;
+}
+
+// Cross-tile workspace for `ntiles` tiles in total over `ngroups` windows:
+// boundary sites (16 values per tile), two flags per tile, double-buffered
+// parameter partials (35 per tile), four sync words per window.
+int ensure_tilespace(pimc_ctx* c, size_t ntiles, size_t ngroups) {
+  if (ntiles <= c->tile_cap && ngroups <= c->group_cap) return PIMC_OK;
+  if (c->halo && hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
+  ntiles = std::max(ntiles, c->tile_cap);
+  ngroups = std::max(ngroups, c->group_cap);
+  void** bufs[] = {&c->halo, (void**)&c->hflag, (void**)&c->wpart, (void**)&c->wsync};
+  for (void** q : bufs) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  c->tile_cap = c->group_cap = 0;
+  const bool ok = hipMalloc(&c->halo, ntiles * 16 * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&c->hflag, ntiles * 2 * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc(&c->wpart, 2 * ntiles * 35 * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&c->wsync, ngroups * 4 * sizeof(uint32_t)) == hipSuccess;
+  if (!ok) return PIMC_ERR_NOMEM;
+  c->tile_cap = ntiles;
+  c->group_cap = ngroups;
   return PIMC_OK;
 }
 
@@ -227,10 +252,7 @@ int pimc_ctx_create(pimc_ctx** out, int device) {
   }
   if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
   if (const char* e = std::getenv("PIMC_NO_GRAPHS")) c->no_graphs = std::atoi(e) != 0;
-  bool ok = hipMalloc(&c->halo, (size_t)MAX_TILES * 16 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->hflag, (size_t)MAX_TILES * 2 * sizeof(uint32_t)) == hipSuccess &&
-            hipMalloc(&c->wpart, (size_t)2 * MAX_TILES * 35 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->wsync, 16 * sizeof(uint32_t)) == hipSuccess;
+  bool ok = ensure_tilespace(c, MAX_TILES, 4) == PIMC_OK;
   int khz = 0;
   ok = ok && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0;
   if (!ok) {
@@ -412,7 +434,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   std::vector<int64_t> Ms(B);
   for (int i = 0; i < B; ++i) {
     const int64_t Mi = b->offsets[i + 1] - b->offsets[i] - 1;
-    if (Mi < 1) return PIMC_ERR_ARG;
+    if (Mi < 1 || Mi >= (1ll << 30)) return PIMC_ERR_ARG;
     Ms[i] = Mi;
     maxM = std::max(maxM, Mi);
   }
@@ -422,15 +444,36 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   if (r) return r;
   const bool fp64 = b->prec == PIMC_FP64;
   int NT = 0, stage = 0, T = 1;
-  const int K = choose_shape(ctx, maxM, fp64, false, NT, stage, T);
+  int K = 0;
+  // Time tiles (set_sweep_tiles > 1) apply when every window of the batch
+  // needs exactly that many tiles of the chosen shape; otherwise one
+  // workgroup per window.
+  if (ctx->tiles > 1 && !fp64) {
+    K = choose_shape(ctx, maxM, fp64, true, NT, stage, T);
+    const int64_t S = (int64_t)NT * K;
+    for (int i = 0; K && i < B; ++i)
+      if (!((T - 1) * S < Ms[i] && Ms[i] <= T * S)) K = 0;
+  }
+  if (!K) {
+    T = 1;
+    K = choose_shape(ctx, maxM, fp64, false, NT, stage, T);
+  }
   if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);
   a.stage = stage;
   a.stride = 1;
-  a.tiles = 1;
+  a.tiles = T;
   a.ngroups = B;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
   if ((r = ensure_batch(ctx, (size_t)B))) return r;
+  if (T > 1) {
+    if ((r = ensure_tilespace(ctx, (size_t)B * T, (size_t)B))) return r;
+    a.halo = ctx->halo;
+    a.hflag = ctx->hflag;
+    a.wpart = ctx->wpart;
+    a.wsync = ctx->wsync;
+    a.spin_ticks = ctx->spin_ticks;
+  }
   // longest windows first, so the tail of the launch holds the short ones
   std::vector<int32_t> order(B);
   std::iota(order.begin(), order.end(), 0);
@@ -464,7 +507,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     a.stride = stats->stride > 1 ? stats->stride : 1;
   }
   a.err = ctx->err;
-  return pimc::launch_sweep(a, fp64, K, B, NT, s);
+  return pimc::launch_sweep(a, fp64, K, B * T, NT, s);
 }
 
 }  // extern "C"

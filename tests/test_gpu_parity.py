@@ -325,6 +325,45 @@ def test_batch_window_equals_single_run(ctx):
         np.testing.assert_allclose(pb.cpu().numpy(), win.p.cpu().numpy(), rtol=1e-14)
 
 
+@pytest.mark.parametrize("Ms,T", [([4096, 3500, 3073], 4), ([4096, 600, 2000], 4), ([8192, 8000], 8)])
+def test_tiled_batch_equals_single_runs(ctx, Ms, T):
+    """Windows that all need T tiles run tiled inside the batch (B x T
+    workgroups); a ragged batch falls back to one workgroup per window.
+    Either way every window's chain and statistics equal its own untiled
+    run (tiling changes only the rounding of the parameter sums)."""
+    probs = [W.make_hh_problem(M, 0.02, 400 + i, require_spike=False) for i, M in enumerate(Ms)]
+    spec = probs[0].model
+    chains = [11 + i for i in range(len(Ms))]
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+    n = 12
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], chains, "fp32")
+    dev = batch.X.device
+    bst = P.SweepStats(sum=torch.zeros(batch.X.shape, dtype=torch.float64, device=dev),
+                       sumsq=torch.zeros(batch.X.shape, dtype=torch.float64, device=dev), xref=batch.X.clone(),
+                       ptrace=torch.zeros((len(Ms), n, 7), dtype=torch.float64, device=dev),
+                       acc=torch.zeros((len(Ms), 10), dtype=torch.int64, device=dev), burn=0)
+    ctx.set_tiles(T)
+    try:
+        print(f"tiled batch Ms={Ms} T={T}", flush=True)
+        P.pimc_run_batch(ctx, spec, batch, seed=8, sweep0=3, w=w, n_sweeps=n, stats=bst)
+        assert ctx.sync() == 0
+        for i, q in enumerate(probs):
+            ctx.set_tiles(1)
+            win = P.Window.from_arrays(q.X0, q.p0, q.y, q.I, "fp32")
+            st = P.SweepStats.allocate(win, n, burn=0)
+            P.pimc_sweep(ctx, spec, win, seed=8, chain=chains[i], sweep0=3, w=w, n_sweeps=n, stats=st)
+            assert ctx.sync() == 0
+            a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
+            np.testing.assert_array_equal(batch.X[a:b].cpu().numpy(), win.X.cpu().numpy())
+            np.testing.assert_allclose(batch.p[i].cpu().numpy(), win.p.cpu().numpy(), rtol=1e-14)
+            np.testing.assert_array_equal(bst.acc[i].cpu().numpy(), st.acc.cpu().numpy())
+            np.testing.assert_allclose(bst.ptrace[i].cpu().numpy(), st.ptrace.cpu().numpy(), rtol=1e-14)
+            np.testing.assert_allclose(bst.sum[a:b].cpu().numpy(), st.sum.cpu().numpy(), rtol=1e-12, atol=1e-12)
+    finally:
+        ctx.set_tiles(0)
+
+
 def test_param_update_entry_point(ctx):
     prob = _problem(256)
     X = _perturbed(prob, 6)

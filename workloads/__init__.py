@@ -17,10 +17,10 @@ stands in for it.
 from .problem import Problem, ModelSpec, P_STAR, GATES_MHN, default_model
 from .hh_data import make_hh_problem, hh_stimulus, hh_truth
 from .lin1_data import make_lin1_problem
-from .configs import CONFIGS, config_problem
+from .configs import CONFIGS, MASK_ALL, MASK_C1, batch_sizes, batch_true_params, config_batch, config_problem
 
 __all__ = [
     "Problem", "ModelSpec", "P_STAR", "GATES_MHN", "default_model",
     "make_hh_problem", "hh_stimulus", "hh_truth", "make_lin1_problem",
-    "CONFIGS", "config_problem",
+    "CONFIGS", "MASK_ALL", "MASK_C1", "batch_sizes", "batch_true_params", "config_batch", "config_problem",
 ]

@@ -50,3 +50,23 @@ def batch_true_params(B: int, seed: int = 104) -> np.ndarray:
     """Per-window true parameters: the Table 2 values scaled by U(0.8, 1.2)."""
     rng = np.random.default_rng(seed + 1)
     return np.asarray(P_STAR) * rng.uniform(0.8, 1.2, size=(B, 7))
+
+
+def _batch_window(args):
+    w, M, p_true, dt, mask, data_seed = args
+    model = ModelSpec(dt=dt, p_mask=mask)
+    return make_hh_problem(int(M), dt, data_seed + w, model=model, p_true=p_true, chain=w, require_spike=False)
+
+
+def config_batch(name: str = "c4", B: int | None = None, workers: int = 8):
+    """The windows of the batched workload: own sizes, drives, noise and true parameters."""
+    c = CONFIGS[name]
+    B = B or c["B"]
+    sizes = batch_sizes(c["B"], c["M_lo"], c["M_hi"], c["data_seed"])[:B]
+    ptrue = batch_true_params(c["B"], c["data_seed"])[:B]
+    jobs = [(w, sizes[w], ptrue[w], c["dt"], c["p_mask"], c["data_seed"]) for w in range(B)]
+    if workers <= 1:
+        return [_batch_window(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_window, jobs, chunksize=4)

@@ -218,7 +218,8 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* bat
 
 /* Statistics of pimc_hmc (every pointer nullable; device memory).
  *   acc     [B][PIMC_NACC] int64 (+=): [0] accepted proposals, [1] proposals
- *           whose trajectory left the box, [9] non-finite energy changes
+ *           whose trajectory was invalid (a coordinate outside its box after
+ *           a reflection), [9] non-finite energy changes
  *   ptrace  [B][n_proposals][7] FP64: p after every proposal (written)
  *   dH      [B][n_proposals] FP64: H1 - H0 of every proposal (written) */
 typedef struct {
@@ -233,7 +234,11 @@ typedef struct {
  *   momenta r ~ N(0, 1/minv) (Philox MOM / PMOM addresses of proposal k),
  *   L leapfrog steps of size eps driven by dA/d(X, p) (the local stencil of
  *   pimc_grad), H = A + 1/2 sum r^2 minv in FP64, accept iff log u < -dH
- *   (u at the HACC address) and no position left the box at any step.
+ *   (u at the HACC address) and the trajectory stayed valid.  A coordinate
+ *   that a drift carries across a wall of its box is reflected back and its
+ *   momentum component negated (Neal 2011, Section 5.1); one reflection per
+ *   drift, and a coordinate still outside after it invalidates the
+ *   trajectory.
  * Proposal indices are k0 .. k0 + n_proposals - 1.  minv: HOST FP64 [11],
  * inverse masses of (V, m, h, n) then p1..p7 (unsampled parameters never
  * move).  eps > 0, L >= 1.  Positions and parameters are updated in place.

@@ -11,9 +11,14 @@ parameter:
   L leapfrog steps of size e:  r -= e/2 dA/dq;  q += e r / m;  r -= e/2 dA/dq
   accept iff log u < -(H_L - H_0)   (u from the HACC address)
 
-A trajectory whose position leaves the box at any step is rejected (the
-reverse trajectory visits the same points, so the rule is symmetric).
-Unsampled parameters keep zero momentum and never move.
+Box walls: a coordinate that a drift carries across a wall of its box is
+reflected back into the box and its momentum negated (the standard handling
+of constraints in HMC: Neal, "MCMC using Hamiltonian dynamics", 2011,
+Section 5.1); the map stays reversible and volume preserving, so the target
+(exp(-A) on the box) is unchanged.  One reflection per drift: a coordinate
+still outside after it (a drift longer than the box) makes the trajectory
+invalid, and an invalid trajectory is rejected.  Unsampled parameters keep
+zero momentum and never move.
 """
 
 from __future__ import annotations
@@ -41,9 +46,21 @@ def kinetic(r, rp, minv_state, minv_param):
         0.5 * float((rp * rp * np.asarray(minv_param)).sum())
 
 
-def leapfrog(spec, X, p, y, I, r, rp, mask, e, L, minv_state, minv_param):
-    """L leapfrog steps from (X, p, r, rp); returns the end point and whether
-    every intermediate position stayed inside the box."""
+def reflect(q, r, lo, hi):
+    """One reflection at the box walls: returns (q', r', n_reflected, inside)."""
+    below = q < lo
+    above = q > hi
+    q = np.where(below, 2.0 * lo - q, np.where(above, 2.0 * hi - q, q))
+    r = np.where(below | above, -r, r)
+    inside = bool(((q >= lo) & (q <= hi)).all())
+    return q, r, int((below | above).sum()), inside
+
+
+def leapfrog(spec, X, p, y, I, r, rp, mask, e, L, minv_state, minv_param, count=None):
+    """L leapfrog steps from (X, p, r, rp) with reflection at the box walls;
+    returns the end point and whether the trajectory stayed valid (every
+    drift ended inside the box after at most one reflection).  `count`, a
+    one-element list, receives the number of reflections."""
     q = X.copy()
     qp = p.copy()
     r = r.copy()
@@ -59,8 +76,13 @@ def leapfrog(spec, X, p, y, I, r, rp, mask, e, L, minv_state, minv_param):
         rp -= 0.5 * e * np.where(mask, gp, 0.0)
         q += e * ms * r
         qp += e * mp_ * rp
-        if not (((q >= lo) & (q <= hi)).all() and ((qp >= plo) & (qp <= phi)).all()):
-            inside = False
+        q, r, n1, ok1 = reflect(q, r, lo[None, :], hi[None, :])
+        qs, rs, n2, ok2 = reflect(qp[mask], rp[mask], plo[mask], phi[mask])
+        qp[mask] = qs
+        rp[mask] = rs
+        inside = inside and ok1 and ok2
+        if count is not None:
+            count[0] += n1 + n2
         g, gp = grad(spec, q, y, I, qp)
         r -= 0.5 * e * g
         rp -= 0.5 * e * np.where(mask, gp, 0.0)

@@ -10,7 +10,13 @@
 //   for s = 1..L:  q(s) = q(s-1) + e minv r(s-1/2);  g(s) = dA/dq at q(s)
 //                  r(s+1/2) = r(s-1/2) - e g(s)  (the last step kicks e/2)
 //   H1 = A(qL) + 1/2 sum rL^2 minv;  accept iff log u < -(H1 - H0)
-//   and no position left the box at any step.
+//   and every drift ended inside the box.
+//
+// A coordinate that a drift carries across a wall of its box is reflected
+// back and its momentum negated (constraint handling by reflection, Neal,
+// "MCMC using Hamiltonian dynamics", 2011, Section 5.1: reversible and volume
+// preserving, so the target exp(-A) on the box is unchanged).  One reflection
+// per drift; a coordinate still outside afterwards invalidates the trajectory.
 //
 // One kernel per leapfrog step over all chains' sites (blocks of 256 sites
 // of one chain, plus one halo site on each side whose drift is recomputed
@@ -103,7 +109,16 @@ __device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, bo
   for (int l = 0; l < 7; ++l) {
     const bool on = (a.m.p_mask >> l) & 1;
     rps[l] = on ? rp_in[l] - c * a.eps * gp_prev[l] : 0.0;
-    ps[l] = on ? p_in[l] + a.eps * a.minv[4 + l] * rps[l] : p_in[l];
+    double q = on ? p_in[l] + a.eps * a.minv[4 + l] * rps[l] : p_in[l];
+    // one reflection at the box walls, momentum negated
+    if (on && q < a.m.p_lo[l]) {
+      q = 2.0 * a.m.p_lo[l] - q;
+      rps[l] = -rps[l];
+    } else if (on && q > a.m.p_hi[l]) {
+      q = 2.0 * a.m.p_hi[l] - q;
+      rps[l] = -rps[l];
+    }
+    ps[l] = q;
   }
 }
 
@@ -118,6 +133,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
   __shared__ T lI[HB + 2];
   __shared__ double red[16];
   __shared__ double lsum[4];
+  __shared__ uint8_t lflip[HB + 2];   // bit c: component c reflected in this drift
   const int t = threadIdx.x;
   const int b = blockIdx.x;
   const int ch = a.bmap[b];
@@ -185,12 +201,24 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
     const int n = site0 - 1 + j;
     if (n >= 0 && n <= M) {
       T q[4];
+      uint32_t flip = 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         q[c] = Qin[(int64_t)n * 4 + c];
-        if (MODE != 0) q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
+        if (MODE != 0) {
+          q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
+          // one reflection at the box walls (the momentum is negated below)
+          if (q[c] < C.lo[c]) {
+            q[c] = (T)2 * C.lo[c] - q[c];
+            flip |= 1u << c;
+          } else if (q[c] > C.hi[c]) {
+            q[c] = (T)2 * C.hi[c] - q[c];
+            flip |= 1u << c;
+          }
+        }
         lq[j][c] = q[c];
       }
+      lflip[j] = (uint8_t)flip;
       const T I = Ip[n];
       lI[j] = I;
       T F[4];
@@ -261,8 +289,12 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       }
       part[9] = kin;
     } else {
+      const uint32_t flip = lflip[j];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) r[c] = Rin[(int64_t)n * 4 + c];
+      for (int c = 0; c < 4; ++c) {
+        r[c] = Rin[(int64_t)n * 4 + c];
+        if ((flip >> c) & 1u) r[c] = -r[c];
+      }
     }
     const T kick = MODE == 1 ? e : e * (T)0.5;
     T rn[4];

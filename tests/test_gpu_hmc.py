@@ -73,7 +73,7 @@ def test_hmc_fp64_matches_oracle(ctx, n):
     gdH = st.dH.cpu().numpy()
     acc = st.acc.cpu().numpy()
     for i, (Xo, po, dHo, oko, uo) in enumerate(ref):
-        inside = np.isfinite(dHo)          # the oracle reports NaN for trajectories that left the box
+        inside = np.isfinite(dHo)          # the oracle reports NaN for invalid trajectories
         np.testing.assert_allclose(gdH[i][inside], dHo[inside], rtol=1e-8, atol=1e-9)
         assert acc[i, 1] == (~inside).sum()
         safe = np.abs(dHo[inside] + np.log(uo[inside])) > 1e-6
@@ -104,7 +104,32 @@ def test_hmc_fp32_close_to_oracle(ctx):
             assert st.acc.cpu().numpy()[i, 0] == int(oko[0])
 
 
-def test_hmc_leaving_box_rejects(ctx):
+def test_hmc_fp64_reflection_matches_oracle(ctx):
+    """Trajectories that cross the gate walls (m within 1e-3 of 1 at the spike
+    peak, gate momenta large): reflections happen and the proposal equals the
+    oracle's."""
+    pr = W.make_hh_problem(400, 0.02, 101, model=W.ModelSpec(p_mask=0x7F), init="truth")
+    minv = np.array([2.5e-3, 1e-4, 1e-4, 1e-4] + list((1e-3 * np.abs(pr.p0)) ** 2))
+    eps, L, seed, k0, n = 0.006, 10, 5, 0, 3
+    cnt = [0]
+    r, rp, mask = OH.momenta(pr.model, seed, 2, k0, pr.M, minv[:4], minv[4:])
+    OH.leapfrog(pr.model, pr.X0, pr.p0, pr.y, pr.I, r, rp, mask, eps, L, minv[:4], minv[4:], count=cnt)
+    assert cnt[0] > 0
+    batch = P.PackedBatch.pack([pr.X0], [pr.p0], [pr.y], [pr.I], [2], "fp64")
+    st = P.HmcStats.allocate(1, n)
+    P.pimc_hmc(ctx, pr.model, batch, seed=seed, k0=k0, eps=eps, L_steps=L, minv=minv, n_proposals=n, stats=st)
+    assert ctx.sync() == 0
+    Xo, po, dHo, oko, uo = _oracle([pr], [2], seed, k0, eps, L, minv, n)[0]
+    assert np.isfinite(dHo).all()
+    np.testing.assert_allclose(st.dH.cpu().numpy()[0], dHo, rtol=1e-8, atol=1e-9)
+    assert (np.abs(dHo + np.log(uo)) > 1e-6).all()
+    acc = st.acc.cpu().numpy()[0]
+    assert acc[0] == oko.sum() == 1 and acc[1] == 0
+    np.testing.assert_allclose(batch.X.cpu().numpy(), Xo, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(batch.p.cpu().numpy()[0], po, rtol=1e-12)
+
+
+def test_hmc_invalid_trajectory_rejects(ctx):
     probs = _chains([64])
     minv = MINV.copy()
     minv[4:] = _minv_p(probs)

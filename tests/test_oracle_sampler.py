@@ -158,6 +158,77 @@ def test_hmc_leapfrog_reversible_and_second_order():
     assert 2.5 < d1 / d2 < 6.0, (d1, d2)
 
 
+def test_hmc_reflection_reversible():
+    """Trajectories that cross the gate walls (m comes within 1e-3 of 1 at
+    the spike peak) are reflected, stay valid, and run back exactly under
+    r -> -r."""
+    P = W.make_hh_problem(400, 0.02, 101, init="truth")
+    spec = P.model
+    assert 1.0 - P.X_true[:, 1].max() < 1e-3
+    minv_s = np.array([2.5e-3, 1e-4, 1e-4, 1e-4])
+    minv_p = (1e-3 * np.abs(P.p_true)) ** 2
+    r, rp, mask = OH.momenta(spec, 5, 0, 0, P.M, minv_s, minv_p)
+    cnt = [0]
+    q, qp, r1, rp1, ok = OH.leapfrog(spec, P.X_true, P.p_true, P.y, P.I, r, rp, mask, 0.02, 10, minv_s, minv_p,
+                                     count=cnt)
+    assert ok and cnt[0] > 0
+    assert (q[:, 1:] >= 0).all() and (q[:, 1:] <= 1).all()
+    cnt2 = [0]
+    q2, qp2, r2, rp2, ok2 = OH.leapfrog(spec, q, qp, P.y, P.I, -r1, -rp1, mask, 0.02, 10, minv_s, minv_p,
+                                        count=cnt2)
+    assert ok2 and cnt2[0] == cnt[0]
+    np.testing.assert_allclose(q2, P.X_true, rtol=0, atol=1e-10 * np.abs(P.X_true).max())
+    np.testing.assert_allclose(qp2, P.p_true, rtol=1e-10)
+    np.testing.assert_allclose(-r2, r, rtol=1e-7, atol=1e-7 * np.abs(r).max())
+
+
+def test_hmc_reflection_samples_truncated_posterior():
+    """HMC with reflecting walls samples the box-truncated posterior: LIN1
+    with M = 1 (two coordinates), moments against a fine grid integral of
+    exp(-A) over the box, A written from the LIN1 definition."""
+    L = W.make_lin1_problem(M=1, dt=0.1, Rd=100.0, Ro=4.0, data_seed=3)
+    lam, dt, Rd, Ro = L.p0[0], L.model.dt, L.model.Rd[0], L.model.Ro
+    a, b = 1 + lam * dt / 2, 1 - lam * dt / 2
+    k1 = 0.5 * dt * (L.I[1] + L.I[0])
+    y1 = L.y[1]
+    lo, hi = y1 - 0.35, y1 + 0.25
+    spec = L.model.with_(x_lo=(lo,), x_hi=(hi,))
+    g = np.linspace(lo, hi, 1601)
+    x0, x1 = np.meshgrid(g, g, indexing="ij")
+    A = 0.5 * Ro * (y1 - x1) ** 2 + 0.5 * Rd * (a * x1 - b * x0 - k1) ** 2
+    wgt = np.exp(-(A - A.min()))
+    wgt[0, :] *= 0.5
+    wgt[-1, :] *= 0.5
+    wgt[:, 0] *= 0.5
+    wgt[:, -1] *= 0.5
+    Z = wgt.sum()
+    m_ref = np.array([(wgt * x0).sum(), (wgt * x1).sum()]) / Z
+    v_ref = np.array([(wgt * (x0 - m_ref[0]) ** 2).sum(), (wgt * (x1 - m_ref[1]) ** 2).sum()]) / Z
+    X = np.array([[y1], [y1]])
+    p = L.p0.copy()
+    n = 6000
+    tr = np.empty((n, 2))
+    acc = 0
+    cnt = 0
+    for k in range(n):
+        if k < 500:
+            r, rp, mask = OH.momenta(spec, 12, 0, k, 1, [0.04], [1.0])
+            c = [0]
+            OH.leapfrog(spec, X, p, L.y, L.I, r, rp, mask, 0.12, 6, [0.04], [1.0], count=c)
+            cnt += c[0]
+        X, p, okp, _ = OH.hmc_proposal(spec, X, p, L.y, L.I, seed=12, chain=0, k=k, e=0.12, L=6,
+                                       minv_state=[0.04], minv_param=[1.0])
+        acc += okp
+        tr[k] = X[:, 0]
+    assert cnt > 25               # the walls are hit often
+    assert acc / n > 0.5
+    m = tr.mean(axis=0)
+    z = (m - m_ref) / _batch_mcse(tr, 30)
+    assert np.abs(z).max() < 4.5, (m, m_ref, z)
+    zv = (tr.var(axis=0) - v_ref) / _batch_mcse((tr - m) ** 2, 30)
+    assert np.abs(zv).max() < 4.5, zv
+
+
 @pytest.mark.slow
 def test_hmc_lin1_matches_closed_form():
     L = W.make_lin1_problem(M=16)

@@ -159,8 +159,10 @@ typedef struct {
 int pimc_ctx_create(pimc_ctx** out, int device);
 void pimc_ctx_destroy(pimc_ctx* ctx);
 
-/* Sites per thread of the sweep kernel: 4, 8 or 16 (FP32) / 4 or 8 (FP64);
- * 0 restores the automatic choice.  The chain does not depend on it: random
+/* Sites per thread of the sweep kernel: 2, 4, 8 or 16 (FP32) / 4 (FP64);
+ * 0 restores the automatic choice (which never picks 2).  FP64 windows run
+ * in one workgroup of at most 256 threads, so M <= 1024; longer FP64
+ * windows are refused with PIMC_ERR_UNSUPPORTED.  The chain does not depend on it: random
  * numbers are addressed by (site, sweep), never by thread. */
 int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
 
@@ -171,7 +173,9 @@ int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
  * wait is bounded).  0 restores the automatic choice (one workgroup when the
  * window fits, the fewest tiles otherwise); at most 256.  Only FP32 windows
  * are tiled: an FP64 window that does not fit one workgroup is refused with
- * PIMC_ERR_UNSUPPORTED.  pimc_run_batch always uses one workgroup per window. */
+ * PIMC_ERR_UNSUPPORTED.  pimc_run_batch uses T tiles per window when every
+ * window of the batch needs exactly T tiles of the chosen shape, else one
+ * workgroup per window. */
 int pimc_set_sweep_tiles(pimc_ctx* ctx, int T);
 
 /* Wait for `stream`, then return and clear any deferred device-side error

@@ -24,14 +24,14 @@ def candidates(M: int, prec: str) -> Iterable[Tuple[int, int]]:
     """(K, T) pairs worth timing; K = 0 / T = 0 mean the library's own choice."""
     yield (0, 0)
     if prec == "fp64":
-        for K in (4, 8):
-            yield (K, 1)
         return
     for K in (4, 8, 16):
         yield (K, 1)
     for T in (2, 4, 8, 16, 32, 64, 128):
         if M // T >= 256:
             yield (0, T)
+        if M // T >= 128:
+            yield (2, T)
 
 
 def tune(ctx: Context, spec, win: Window, w: torch.Tensor, *, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
@@ -83,7 +83,7 @@ def batch_candidates(sizes, prec: str) -> Iterable[Tuple[int, int]]:
     back to one workgroup per window where the windows need different tile
     counts, so such candidates simply time that fallback)."""
     yield (0, 1)
-    for K in ((4, 8) if prec == "fp64" else (4, 8, 16)):
+    for K in ((4,) if prec == "fp64" else (4, 8, 16)):
         yield (K, 1)
     if prec == "fp64":
         return

@@ -27,7 +27,6 @@ struct pimc_ctx {
   // cross-tile workspace: tile_cap tiles over group_cap windows (grow-only)
   size_t tile_cap = 0, group_cap = 0;
   void* halo = nullptr;
-  uint32_t* hflag = nullptr;
   double* wpart = nullptr;
   uint32_t* wsync = nullptr;
   uint64_t spin_ticks = 0;
@@ -126,22 +125,22 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
 }
 
 // Cross-tile workspace for `ntiles` tiles in total over `ngroups` windows:
-// boundary sites (16 values per tile), two flags per tile, double-buffered
-// parameter partials (35 per tile), four sync words per window.
+// boundary sites (two slots of 16 generation words per tile), double-buffered
+// parameter partials (70 generation words per tile), four sync words per
+// window (entry barrier and entry check).
 int ensure_tilespace(pimc_ctx* c, size_t ntiles, size_t ngroups) {
   if (ntiles <= c->tile_cap && ngroups <= c->group_cap) return PIMC_OK;
   if (c->halo && hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
   ntiles = std::max(ntiles, c->tile_cap);
   ngroups = std::max(ngroups, c->group_cap);
-  void** bufs[] = {&c->halo, (void**)&c->hflag, (void**)&c->wpart, (void**)&c->wsync};
+  void** bufs[] = {&c->halo, (void**)&c->wpart, (void**)&c->wsync};
   for (void** q : bufs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
   c->tile_cap = c->group_cap = 0;
-  const bool ok = hipMalloc(&c->halo, ntiles * 16 * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&c->hflag, ntiles * 2 * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc(&c->wpart, 2 * ntiles * 35 * sizeof(double)) == hipSuccess &&
+  const bool ok = hipMalloc(&c->halo, ntiles * 2 * 16 * sizeof(uint64_t)) == hipSuccess &&
+                  hipMalloc(&c->wpart, 2 * ntiles * 70 * sizeof(uint64_t)) == hipSuccess &&
                   hipMalloc(&c->wsync, ngroups * 4 * sizeof(uint32_t)) == hipSuccess;
   if (!ok) return PIMC_ERR_NOMEM;
   c->tile_cap = ntiles;
@@ -164,10 +163,16 @@ int64_t stage_room(int NT, int K, bool fp64) {
 // per SIMD, no register spills), else any single-workgroup shape; windows too
 // long for one workgroup are cut into tiles of 256 threads.
 int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles, int& NT, int& stage, int& T) {
-  static const int cand32[] = {4, 8, 16};
-  static const int cand64[] = {4, 8};
+  // K = 2 (FP32 only) is never the automatic choice: it is a tuning option
+  // for windows cut into many tiles, where it halves the sites per thread
+  static const int cand32[] = {4, 8, 16, 2};
+  // FP64 runs only in the spill-free shape (4 sites per thread, at most 256
+  // threads): the wider FP64 shapes spill about 1 KB per thread to scratch,
+  // and one of them (8 sites x 512 threads, M = 4096) faulted the GPU once
+  // without an identified cause, so they are not launched
+  static const int cand64[] = {4};
   const int* cand = fp64 ? cand64 : cand32;
-  const int nc = fp64 ? 2 : 3;
+  const int nc = fp64 ? 1 : (ctx->tile_K == 2 ? 4 : 3);
   const int want_T = allow_tiles ? ctx->tiles : 1;
   if (want_T <= 1) {
     for (int pass = 0; pass < 2; ++pass) {
@@ -176,6 +181,7 @@ int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles,
         if (ctx->tile_K && ctx->tile_K != K) continue;
         const int64_t need = (maxM + K - 1) / K;
         const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
+        if (fp64 && pass == 1) continue;
         const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
         if (nt > lim) continue;
         const int64_t st = stage_room((int)nt, K, fp64);
@@ -274,7 +280,6 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (ctx->offsets) (void)hipFree(ctx->offsets);
   if (ctx->order) (void)hipFree(ctx->order);
   if (ctx->halo) (void)hipFree(ctx->halo);
-  if (ctx->hflag) (void)hipFree(ctx->hflag);
   if (ctx->wpart) (void)hipFree(ctx->wpart);
   if (ctx->wsync) (void)hipFree(ctx->wsync);
   void* hbufs[] = {ctx->hQ1, ctx->hR0, ctx->hR1, ctx->hX0, ctx->hpart, ctx->hp0, ctx->hpbuf, ctx->hrpbuf,
@@ -285,7 +290,7 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
 }
 
 int pimc_set_sweep_tile(pimc_ctx* ctx, int K) {
-  if (!ctx || !(K == 0 || K == 4 || K == 8 || K == 16)) return PIMC_ERR_ARG;
+  if (!ctx || !(K == 0 || K == 2 || K == 4 || K == 8 || K == 16)) return PIMC_ERR_ARG;
   ctx->tile_K = K;
   return PIMC_OK;
 }
@@ -385,7 +390,6 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   a.tiles = T;
   a.ngroups = 1;
   a.halo = ctx->halo;
-  a.hflag = ctx->hflag;
   a.wpart = ctx->wpart;
   a.wsync = ctx->wsync;
   a.spin_ticks = ctx->spin_ticks;
@@ -469,8 +473,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   if (T > 1) {
     if ((r = ensure_tilespace(ctx, (size_t)B * T, (size_t)B))) return r;
     a.halo = ctx->halo;
-    a.hflag = ctx->hflag;
-    a.wpart = ctx->wpart;
+      a.wpart = ctx->wpart;
     a.wsync = ctx->wsync;
     a.spin_ticks = ctx->spin_ticks;
   }

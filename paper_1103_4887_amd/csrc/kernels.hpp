@@ -47,9 +47,8 @@ struct SweepArgs {
   // time tiles (tiles == 1: a window is one workgroup, no global memory sync)
   int32_t tiles;
   int32_t ngroups;     // number of windows in the launch
-  void* halo;          // [ngroups*tiles][16] boundary sites (path precision)
-  uint32_t* hflag;     // [ngroups*tiles][2] generations of the first / last boundary site
-  double* wpart;       // [2][ngroups][tiles][35] partial sums of the parameter statistics
+  void* halo;          // [ngroups*tiles][2][16] generation words: first / last boundary site
+  void* wpart;         // [2][ngroups][tiles][70] generation words: partial sums of the parameter statistics
   uint32_t* wsync;     // [ngroups][4]: arrival counter, entry-check flag
   uint64_t spin_ticks; // wall-clock ticks a wait may last
 };

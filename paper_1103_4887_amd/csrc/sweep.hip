@@ -41,9 +41,48 @@ struct Nb {  // a neighbour site: state and cached F
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, 0xF, 0xF, false);
-  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  // every lane reads a lane of its own row, so no lane keeps an old value
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Wave-uniform values that the site updates read on every iteration are
+// held in vector registers: the kernel's uniform state (pointers, counters,
+// model constants) exceeds the scalar register file, and values the compiler
+// leaves in scalar registers are then spilled to vector lanes and read back
+// with one v_readlane per use.  The copy goes through an opaque move, so the
+// compiler cannot turn it back into a scalar.
+__device__ __forceinline__ float in_vgpr(float x) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ __forceinline__ double in_vgpr(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_bit_cast(uint32_t, in_vgpr(__builtin_bit_cast(float, (uint32_t)b)));
+  const uint32_t hi = __builtin_bit_cast(uint32_t, in_vgpr(__builtin_bit_cast(float, (uint32_t)(b >> 32))));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ void consts_in_vgprs(Consts<T>& C) {
+  C.h = in_vgpr(C.h);
+  C.half_Ro = in_vgpr(C.half_Ro);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    C.half_beta_Rd[a] = in_vgpr(C.half_beta_Rd[a]);
+    C.lo[a] = in_vgpr(C.lo[a]);
+    C.hi[a] = in_vgpr(C.hi[a]);
+  }
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    C.Va[g] = in_vgpr(C.Va[g]);
+    C.inv_dVa[g] = in_vgpr(C.inv_dVa[g]);
+    C.tau0[g] = in_vgpr(C.tau0[g]);
+    C.tau1[g] = in_vgpr(C.tau1[g]);
+  }
+#pragma unroll
+  for (int l = 0; l < 7; ++l) C.p[l] = in_vgpr(C.p[l]);
 }
 
 // Sum over each row of 16 lanes with DPP (quad_perm xor 1, xor 2, then
@@ -73,7 +112,8 @@ __device__ __forceinline__ bool accept_u(uint32_t uword, double dA) {
 // `ticks` of the constant wall clock the error flag gets bit 2 and the wait
 // gives up, so a workgroup can never wait forever on a missing partner.
 __device__ __forceinline__ void wait_ge(uint32_t* p, uint32_t target, uint32_t* err, uint64_t ticks) {
-  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+      !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u)) {
     const uint64_t t0 = wall_clock64();
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
@@ -183,6 +223,104 @@ __device__ __forceinline__ void lds_get(const Consts<T>& C, const T* slot, T I, 
   nb.F[0] = hh_FV(C, nb.x[0], nb.x[1], nb.x[2], nb.x[3], I);
 }
 
+// ---- exchange between the time tiles of a window -------------------------
+// Every value crosses as "generation words": a 32-bit payload and the 32-bit
+// generation it belongs to, written and read as one 64-bit relaxed atomic at
+// agent scope.  A reader that sees the generation it waits for holds that
+// generation's payload, so neither a separate flag nor a release/acquire
+// fence (an L2 write-back and invalidate on this chip) is needed: one
+// memory round trip per exchange.  The protocol guarantees that a slot is
+// never overwritten by a later generation before its reader has consumed it
+// (boundary sites: the writer needs the reader's progress first; partial
+// sums: double-buffered by sweep parity).
+constexpr int SLOT_WORDS = 16;   // one site: 7 values, two words each in FP64
+
+__device__ __forceinline__ uint64_t gen_word(uint32_t gen, uint32_t payload) {
+  return ((uint64_t)gen << 32) | payload;
+}
+__device__ __forceinline__ void gw_store(uint64_t* p, uint64_t w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t gw_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Load n words (all in flight together) until each carries generation >= gen.
+// A wait that outlasts `ticks` sets error bit 4 and returns what it has.
+template <int N>
+__device__ __forceinline__ void gw_wait(const uint64_t* const (&src)[N], uint64_t (&w)[N], uint32_t gen,
+                                        uint32_t* err, uint64_t ticks) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    w[i] = gw_load(src[i]);
+    ok = ok && (uint32_t)(w[i] >> 32) >= gen;
+  }
+  if (ok) return;
+  // after one timed-out wait every later wait gives up at once, so a broken
+  // exchange ends the launch quickly (with the error reported) instead of
+  // timing out once per sweep
+  if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u) return;
+  const uint64_t t0 = wall_clock64();
+  while (true) {
+    __builtin_amdgcn_s_sleep(1);
+    ok = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      w[i] = gw_load(src[i]);
+      ok = ok && (uint32_t)(w[i] >> 32) >= gen;
+    }
+    if (ok) return;
+    if (wall_clock64() - t0 > ticks) {
+      atomicOr(err, 4u);
+      return;
+    }
+  }
+}
+
+// Publish a boundary site (x and the gates' F) as generation `gen`.
+template <typename T>
+__device__ __forceinline__ void site_publish(uint64_t* slot, const T (&x)[4], const T (&F)[4], uint32_t gen) {
+  const T v[7] = {x[0], x[1], x[2], x[3], F[1], F[2], F[3]};
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    if constexpr (sizeof(T) == 4) {
+      gw_store(slot + i, gen_word(gen, __builtin_bit_cast(uint32_t, v[i])));
+    } else {
+      const uint64_t b = __builtin_bit_cast(uint64_t, v[i]);
+      gw_store(slot + 2 * i, gen_word(gen, (uint32_t)b));
+      gw_store(slot + 2 * i + 1, gen_word(gen, (uint32_t)(b >> 32)));
+    }
+  }
+}
+
+// Wait for generation `gen` of a published boundary site and read it (dV/dt
+// recomputed with the current parameters, as for an LDS neighbour).
+template <typename T>
+__device__ __forceinline__ void site_fetch(const Consts<T>& C, const uint64_t* slot, uint32_t gen, T I, Nb<T>& nb,
+                                           uint32_t* err, uint64_t ticks) {
+  constexpr int N = sizeof(T) == 4 ? 7 : 14;
+  const uint64_t* src[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) src[i] = slot + i;
+  uint64_t w[N];
+  gw_wait<N>(src, w, gen, err, ticks);
+  T v[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    if constexpr (sizeof(T) == 4)
+      v[i] = __builtin_bit_cast(T, (uint32_t)w[i]);
+    else
+      v[i] = __builtin_bit_cast(T, ((uint64_t)(uint32_t)w[2 * i + 1] << 32) | (uint32_t)w[2 * i]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) nb.x[a] = v[a];
+  nb.F[1] = v[4];
+  nb.F[2] = v[5];
+  nb.F[3] = v[6];
+  nb.F[0] = hh_FV(C, nb.x[0], nb.x[1], nb.x[2], nb.x[3], I);
+}
+
 // Hide a value from loop-invariant code motion.  Without it the compiler
 // hoists the sweep-independent first Philox round of every owned site (and
 // the data-only parts of the parameter statistics) out of the sweep loop and
@@ -245,21 +383,21 @@ template <> struct ThetaMove<6> { static constexpr int ia = 6, ib = -1; };
 __host__ __device__ constexpr int symi(int a, int b) { return a <= b ? sym7(a, b) : sym7(b, a); }
 
 // One Metropolis move of parameter L against the sufficient statistics.
-// z: proposal step; uword, lu32: Philox word of the accept uniform and its
-// FP32 logarithm (both drawn beforehand).  Written without branches except
-// the rare FP64 re-evaluation of log u near a tie, to keep the sequential
-// chain of the seven moves short.
+// pl: proposed value, drawn and box-tested beforehand (a move of p_l leaves
+// every other p_j unchanged, so p_l before its own move is known when the
+// sweep's parameter section starts); NaN when outside the box.  uword, lu32:
+// Philox word of the accept uniform and its FP32 logarithm.  cA = beta Rd_V / 2.
+// Written without branches except the rare FP64 re-evaluation of log u near
+// a tie, to keep the sequential chain of the seven moves short.
 template <int L>
-__device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_t uword, float lu32,
-                                           const double (&wpar)[7], double (&pd)[7], double (&s)[7],
-                                           const double (&G)[28], bool& changed, int& acc, int& nonfin, bool rec,
-                                           int win) {
+__device__ __forceinline__ void param_move(const SweepArgs& a, double pl, uint32_t uword, float lu32, double cA,
+                                           double (&pd)[7], double (&s)[7], const double (&G)[28], bool& changed,
+                                           int& acc, int& nonfin, bool rec, int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
   constexpr int ia = ThetaMove<L>::ia;
   constexpr int ib = ThetaMove<L>::ib;
   constexpr int ibb = ib >= 0 ? ib : 0;
-  const double pl = pd[L] + wpar[L] * z;
-  const bool inbox = pl >= a.m.p_lo[L] && pl <= a.m.p_hi[L];
+  const bool inbox = pl == pl;
   const double dp = pl - pd[L];
   // p1, p2, p4, p6 move theta_L directly (p2, p4, p6 also p_L p_{L+1});
   // p3, p5, p7 move theta_L = p_{L-1} p_L
@@ -271,7 +409,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_
     quad += 2.0 * da * db * G[symi(ia, ibb)] + db * db * G[symi(ibb, ibb)];
     lin += db * s[ibb];
   }
-  const double dA = 0.5 * a.m.beta * a.m.Rd[0] * (quad - 2.0 * lin);
+  const double dA = cA * (quad - 2.0 * lin);
   const bool fin = __builtin_isfinite(dA);
   const double gap = -dA - (double)lu32;
   const double E = 1e-5 * (1.0 + (double)__builtin_fabsf(lu32));
@@ -299,7 +437,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double z, uint32_
 
 template <typename T, int K, int MAXT, bool DBG>
 __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
-  static_assert(K % 4 == 0, "K must be a multiple of 4");
+  static_assert(K == 2 || K % 4 == 0, "K must be 2 or a multiple of 4");
   extern __shared__ __align__(16) unsigned char smem[];
   const int NT = blockDim.x;
   const int t = threadIdx.x;
@@ -334,10 +472,10 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   T* lfirst = (T*)smem;                           // [NT][8] first site of each thread
   T* llast = lfirst + NT * 8;                     // [NT][8] last site of each thread
   T* lyi = llast + NT * 8;                        // [S+2][2] (y_n, I_n), n = tile0-1 .. tile0+S
-  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [NRED][4*NW] row partials
+  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [4*NW][NRED] row partials
   double* lstat = lred + NRED * 4 * NW;           // [NRED]
-  double* ldraw = lstat + NRED;                   // [24]: z_l, accept word, FP32 log u_l
-  int* lcnt = (int*)(ldraw + 24);                 // [16]
+  double* ldraw = lstat + NRED;                   // [32]: p_l', accept word, FP32 log u_l, current p
+  int* lcnt = (int*)(ldraw + 32);                 // [16]
   T* lstage = (T*)(lcnt + 16);                    // [stage][4] statistics staging
 
   Consts<T> C;
@@ -349,12 +487,17 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #pragma unroll
   for (int l = 0; l < 7; ++l) pd[l] = P[l];
   C.set_p(pd);
+  // one wave per SIMD leaves room for the model constants in vector
+  // registers; with two, register pressure decides otherwise
+  constexpr bool VCONST = MAXT <= 256;
+  if constexpr (VCONST) consts_in_vgprs(C);
   T ws[4];
   double wpar[7];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) ws[c] = (T)a.w[c];
+  for (int c = 0; c < 4; ++c) ws[c] = VCONST ? in_vgpr((T)a.w[c]) : (T)a.w[c];
 #pragma unroll
   for (int l = 0; l < 7; ++l) wpar[l] = a.w[4 + l];
+  const double cA = 0.5 * a.m.beta * a.m.Rd[0];
   const bool uniform_prop = a.m.proposal == PIMC_PROP_UNIFORM;
   const double hD = 0.5 * a.m.dt;
 
@@ -378,15 +521,15 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
   const bool active = t < NTneed;
   const int n0 = tile0 + t * K;
   const bool has_extra = last_tile && (t == NTneed - 1) && (K * NTneed == M - tile0);
-  // cross-tile halo: boundary sites of each tile in global memory
+  // cross-tile halo: boundary sites of each tile in global memory, slot
+  // [gt][0] the tile's first site, [gt][1] its last.  A single-tile window
+  // never touches it; neighbours that do not exist alias this tile's own
+  // slots, so every address formed is a valid one
   const int gt = bi * tiles + tb;                 // global tile index
-  // [0..7] first, [8..15] last site; a single-tile window never touches it
-  // (it then points at this workgroup's own LDS exchange slot)
-  T* hmine = (tiles > 1 && a.halo) ? (T*)a.halo + (int64_t)gt * 16 : lfirst + t * 8;
-  // neighbouring tiles' halo slots; where a neighbour does not exist they
-  // alias this tile's own slot, so every address formed is a valid one
-  const T* hprev = tb > 0 ? (const T*)a.halo + (int64_t)(gt - 1) * 16 : hmine;
-  const T* hnext = !last_tile ? (const T*)a.halo + (int64_t)(gt + 1) * 16 : hmine;
+  uint64_t* hfirst = (tiles > 1 && a.halo) ? (uint64_t*)a.halo + (int64_t)gt * 2 * SLOT_WORDS : (uint64_t*)lred;
+  uint64_t* hlast = (tiles > 1 && a.halo) ? hfirst + SLOT_WORDS : hfirst;
+  const uint64_t* hprev_last = tb > 0 ? hfirst - SLOT_WORDS : hlast;
+  const uint64_t* hnext_first = !last_tile ? hfirst + 2 * SLOT_WORDS : hfirst;
   // LDS index of the extra site's (y, I): site M when this thread owns it,
   // else the tile's first site, so that no evaluation of the expression
   // (speculative or not) leaves the tile's LDS block
@@ -430,11 +573,11 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     // every tile learns whether any tile failed the entry check, and the
     // boundary sites are published before the first sweep
     if (__syncthreads_or(bad) && t == 0) atomicOr(&a.wsync[bi * 4 + 1], 1u);
-    if (t == 0) lds_put(hmine, x[0], F[0]);
-    if (t == NT - 1 && !last_tile) {
-      lds_put(hmine + 8, x[K - 1], F[K - 1]);
-      __hip_atomic_store(&a.hflag[gt * 2 + 1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    // generation 1: the entry state of both boundary sites; after the even
+    // half-sweep of sweep it the first site is generation it + 2, after the
+    // odd half-sweep the last site is generation it + 2
+    if (t == 0) site_publish(hfirst, x[0], F[0], 1u);
+    if (t == NT - 1 && !last_tile) site_publish(hlast, x[K - 1], F[K - 1], 1u);
     tile_barrier(&a.wsync[bi * 4], (uint32_t)tiles, a.err, a.spin_ticks);
     bad = __hip_atomic_load(&a.wsync[bi * 4 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   }
@@ -446,10 +589,15 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
     lds_put(lfirst + t * 8, x[0], F[0]);
     lds_put(llast + t * 8, x[K - 1], F[K - 1]);
   }
+  if (t == 0) {
+#pragma unroll
+    for (int l = 0; l < 7; ++l) ldraw[24 + l] = pd[l];
+  }
   __syncthreads();
   uint32_t nbar = 1;   // tile barriers passed so far (the entry barrier)
 
   int accE = 0, accO = 0, nonfin = 0;
+  T xnx[4] = {0, 0, 0, 0};   // last thread of a tile: the next tile's first site
   int accP[7] = {0, 0, 0, 0, 0, 0, 0};
   T* dx_t = DBG && a.dbg_xprop ? (T*)a.dbg_xprop + (base + n0) * 4 : nullptr;
   double* ddA_t = DBG && a.dbg_dA ? a.dbg_dA + base + n0 : nullptr;
@@ -461,16 +609,29 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 
     if (a.flags & PIMC_STATES) {
       // ---- even half-sweep ----------------------------------------------
+      // accept words: block n >> 2 of the SACC stream holds word n & 3 for
+      // sites n .. n + 3; with K = 2 two threads share a block (n0 is even)
+      constexpr int KS = K < 4 ? K : 4;
       uint32_t uodd[K / 2];
 #pragma unroll
-      for (int q = 0; q < K / 4; ++q) {
+      for (int q = 0; q < (K + 3) / 4; ++q) {
         const int j0 = 4 * q;
         U4 ub{0, 0, 0, 0};
         if (active && n0 + j0 <= M) ub = draw(key, opaque((uint32_t)((n0 + j0) >> 2)), k, TAG_SACC);
-        uodd[2 * q] = ub.y;
-        uodd[2 * q + 1] = ub.w;
+        uint32_t ueven[2];
+        if constexpr (K >= 4) {
+          ueven[0] = ub.x;
+          ueven[1] = ub.z;
+          uodd[2 * q] = ub.y;
+          uodd[2 * q + 1] = ub.w;
+        } else {
+          const bool upper = (n0 & 2) != 0;
+          ueven[0] = upper ? ub.z : ub.x;
+          ueven[1] = 0u;
+          uodd[0] = upper ? ub.w : ub.y;
+        }
 #pragma unroll
-        for (int jj = 0; jj < 4; jj += 2) {
+        for (int jj = 0; jj < KS; jj += 2) {
           const int j = j0 + jj;
           const int nn = n0 + j;
           if (active && nn <= M) {
@@ -479,8 +640,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             if (j == 0) {
               if (hasL) {
                 if (t == 0) {   // last site of the previous tile, after its odd half-sweep
-                  wait_ge(&a.hflag[(gt - 1) * 2 + 1], (uint32_t)it + 1, a.err, a.spin_ticks);
-                  lds_get(C, hprev + 8, lyb[2 * nn - 1], L);
+                  site_fetch(C, hprev_last, (uint32_t)it + 1, lyb[2 * nn - 1], L, a.err, a.spin_ticks);
                 } else {
                   lds_get(C, llast + (t - 1) * 8, lyb[2 * nn - 1], L);
                 }
@@ -502,7 +662,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             double dA;
             T xp[4];
             const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyb[2 * nn], lyb[2 * nn + 1], hasL, L,
-                                        hasR, R, nn >= 1, blk, jj == 0 ? ub.x : ub.z, dA, xp, nonfin);
+                                        hasR, R, nn >= 1, blk, ueven[jj >> 1], dA, xp, nonfin);
             accE += ok;
             if (DBG && last) {
               if (dx_t)
@@ -525,10 +685,11 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         }
         const U4 blk = draw(key, opaque((uint32_t)M), k, TAG_SITE);
         const U4 ub = draw(key, opaque((uint32_t)(M >> 2)), k, TAG_SACC);
+        const uint32_t uM = (M & 2) ? ub.z : ub.x;   // M is even
         double dA;
         T xp[4];
         const bool ok = site_update(C, ws, uniform_prop, xe, Fe, lyb[2 * me], lyb[2 * me + 1], true, L, false, R,
-                                    true, blk, ub.x, dA, xp, nonfin);
+                                    true, blk, uM, dA, xp, nonfin);
         accE += ok;
         if (DBG && last) {
           if (dx_t)
@@ -539,10 +700,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         }
       }
       if (active) lds_put(lfirst + t * 8, x[0], F[0]);
-      if (tiles > 1 && t == 0) {
-        lds_put(hmine, x[0], F[0]);
-        __hip_atomic_store(&a.hflag[gt * 2], (uint32_t)it + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (tiles > 1 && t == 0) site_publish(hfirst, x[0], F[0], (uint32_t)it + 2);
       __syncthreads();
 
       // ---- odd half-sweep -----------------------------------------------
@@ -566,8 +724,9 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
                   R.F[c] = Fe[c];
                 }
               } else if (t == NT - 1) {   // first site of the next tile, after its even half-sweep
-                wait_ge(&a.hflag[(gt + 1) * 2], (uint32_t)it + 1, a.err, a.spin_ticks);
-                lds_get(C, hnext, lyb[2 * nn + 3], R);
+                site_fetch(C, hnext_first, (uint32_t)it + 2, lyb[2 * nn + 3], R, a.err, a.spin_ticks);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xnx[c] = R.x[c];   // kept for the link statistics
               } else {
                 lds_get(C, lfirst + (t + 1) * 8, lyb[2 * nn + 3], R);
               }
@@ -595,16 +754,17 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         }
       }
       if (active) lds_put(llast + t * 8, x[K - 1], F[K - 1]);
-      if (tiles > 1 && t == NT - 1 && !last_tile) {
-        lds_put(hmine + 8, x[K - 1], F[K - 1]);
-        __hip_atomic_store(&a.hflag[gt * 2 + 1], (uint32_t)it + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (tiles > 1 && t == NT - 1 && !last_tile) site_publish(hlast, x[K - 1], F[K - 1], (uint32_t)it + 2);
     }
 
     if (a.flags & PIMC_PARAMS) {
       // ---- random numbers of the parameter moves (path independent), spread
-      //      over the waves: wave w, lane i draws for parameter w + i NW ------
-      {
+      //      over the waves: wave w, lane i draws for parameter w + i NW;
+      //      the proposed value and its box test are formed here too (a move
+      //      of p_l changes no other p_j, so p_l before its move is the value
+      //      at the start of the section).  With time tiles this work fills
+      //      the wait for the other tiles' partial sums ----------------------
+      auto param_draws = [&]() {
         const int l = wv + lane * NW;
         if (lane * NW < 7 && l < 7) {
           const U4 b = draw(key, opaque((uint32_t)l), k, TAG_PARAM);
@@ -619,11 +779,22 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             double z1;
             Math<double>::box_muller(b.x, b.y, z, z1);
           }
-          ldraw[l] = z;
+          // parameter-indexed values by selects (no dynamically indexed
+          // register or argument arrays)
+          double lo = 0.0, hi = 0.0;
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            lo = q == l ? a.m.p_lo[q] : lo;
+            hi = q == l ? a.m.p_hi[q] : hi;
+          }
+          const double pl = ldraw[24 + l] + a.w[4 + l] * z;
+          const bool inbox = pl >= lo && pl <= hi;
+          ldraw[l] = inbox ? pl : __builtin_nan("");
           ldraw[8 + l] = __builtin_bit_cast(double, (uint64_t)b.z);
           ldraw[16 + l] = (double)(__builtin_amdgcn_logf(u01_f(b.z)) * 0.6931471805599453f);
         }
-      }
+      };
+      if (tiles == 1) param_draws();
       // ---- sufficient statistics over the links of the odd sites ----------
       double th[7];
       theta_of(pd, th);
@@ -644,17 +815,22 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
                 if (has_extra) {
                   fr = feat_of(xe, lyb[2 * me + 1]);
                 } else {
-                  // next thread's first site, or the next tile's (already
-                  // awaited during the odd half-sweep when sites moved)
-                  const T* src = lfirst + (t + 1) * 8;
-                  if (t == NT - 1) {
-                    // without site moves the entry publication is current
-                    if (a.flags & PIMC_STATES) wait_ge(&a.hflag[(gt + 1) * 2], (uint32_t)it + 1, a.err, a.spin_ticks);
-                    src = hnext;
-                  }
+                  // next thread's first site, or the next tile's: read during
+                  // the odd half-sweep when sites moved, else the entry
+                  // publication, which is then current
                   T xr[4];
+                  if (t == NT - 1 && (a.flags & PIMC_STATES)) {
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) xr[c] = src[c];
+                    for (int c = 0; c < 4; ++c) xr[c] = xnx[c];
+                  } else if (t == NT - 1) {
+                    Nb<T> nb;
+                    site_fetch(C, hnext_first, 1u, lyb[2 * nn + 3], nb, a.err, a.spin_ticks);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) xr[c] = nb.x[c];
+                  } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) xr[c] = lfirst[(t + 1) * 8 + c];
+                  }
                   fr = feat_of(xr, lyb[2 * nn + 3]);
                 }
               } else {
@@ -672,17 +848,19 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       for (int i = 0; i < NRED; ++i) st[i] = row_sum(st[i]);
       if ((lane & 15) == 15) {
 #pragma unroll
-        for (int i = 0; i < NRED; ++i) lred[i * 4 * NW + wv * 4 + (lane >> 4)] = st[i];
+        for (int i = 0; i < NRED; ++i) lred[(wv * 4 + (lane >> 4)) * NRED + i] = st[i];
       }
       __syncthreads();
       if (t < NRED) {
-        const double* row = lred + t * 4 * NW;
+        // row partials laid out [row][value]: consecutive threads read
+        // consecutive words (no bank conflicts)
+        const double* row = lred + t;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int q = 0; q < 4 * NW; q += 4) {
-          s0 += row[q];
-          s1 += row[q + 1];
-          s2 += row[q + 2];
-          s3 += row[q + 3];
+          s0 += row[q * NRED];
+          s1 += row[(q + 1) * NRED];
+          s2 += row[(q + 2) * NRED];
+          s3 += row[(q + 3) * NRED];
         }
         lstat[t] = (s0 + s1) + (s2 + s3);
       }
@@ -690,10 +868,18 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       if (tiles > 1) {
         // all-reduce over the window's tiles: partials in a double buffer,
         // summed in tile order by every tile (identical results everywhere)
-        double* wp = a.wpart + ((int64_t)(nbar & 1) * a.ngroups * tiles + (int64_t)bi * tiles) * NRED;
-        if (t < NRED) wp[tb * NRED + t] = lstat[t];
+        // every partial value as two generation words, double-buffered by
+        // the parity of the barrier count
+        uint64_t* wp = (uint64_t*)a.wpart +
+                       ((int64_t)(nbar & 1) * a.ngroups * tiles + (int64_t)bi * tiles) * (2 * NRED);
         ++nbar;
-        tile_barrier(&a.wsync[bi * 4], nbar * (uint32_t)tiles, a.err, a.spin_ticks);
+        for (int i = t; i < 2 * NRED; i += NT) {   // 70 words; a tile may have 64 threads
+          const uint64_t b = __builtin_bit_cast(uint64_t, lstat[i >> 1]);
+          gw_store(wp + tb * 2 * NRED + i, gen_word(nbar, (i & 1) ? (uint32_t)(b >> 32) : (uint32_t)b));
+        }
+        // the parameter proposals are drawn while the other tiles' partials
+        // are on their way
+        param_draws();
         // NRED x tiles partials: thread t sums tiles q = t / NRED, + NSEG, ...
         // for value t % NRED with all loads in flight, then NSEG segment sums
         // are combined in segment order (fixed for a given launch shape)
@@ -703,11 +889,20 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           if (sg < NSEG) {
             double acc = 0.0;
             for (int q0 = sg; q0 < tiles; q0 += 8 * NSEG) {
+              const uint64_t* src[16];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u * NSEG < tiles ? q0 + u * NSEG : tb;   // absent: own words, ignored
+                src[2 * u] = wp + q * 2 * NRED + 2 * v;
+                src[2 * u + 1] = src[2 * u] + 1;
+              }
+              uint64_t w[16];
+              gw_wait<16>(src, w, nbar, a.err, a.spin_ticks);
               double vals[8];
 #pragma unroll
               for (int u = 0; u < 8; ++u) {
-                const int q = q0 + u * NSEG;
-                vals[u] = q < tiles ? wp[q * NRED + v] : 0.0;
+                const uint64_t b = ((uint64_t)(uint32_t)w[2 * u + 1] << 32) | (uint32_t)w[2 * u];
+                vals[u] = q0 + u * NSEG < tiles ? __builtin_bit_cast(double, b) : 0.0;
               }
 #pragma unroll
               for (int u = 0; u < 8; ++u) acc += vals[u];
@@ -740,17 +935,23 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         for (int i = 0; i < 28; ++i) G[i] = lstat[7 + i];
         bool changed = false;
         const bool rec = last && t == 0 && tb == 0;
-        param_move<0>(a, zz[0], uw[0], lw[0], wpar, pd, s7, G, changed, accP[0], nonfin, rec, win);
-        param_move<1>(a, zz[1], uw[1], lw[1], wpar, pd, s7, G, changed, accP[1], nonfin, rec, win);
-        param_move<2>(a, zz[2], uw[2], lw[2], wpar, pd, s7, G, changed, accP[2], nonfin, rec, win);
-        param_move<3>(a, zz[3], uw[3], lw[3], wpar, pd, s7, G, changed, accP[3], nonfin, rec, win);
-        param_move<4>(a, zz[4], uw[4], lw[4], wpar, pd, s7, G, changed, accP[4], nonfin, rec, win);
-        param_move<5>(a, zz[5], uw[5], lw[5], wpar, pd, s7, G, changed, accP[5], nonfin, rec, win);
-        param_move<6>(a, zz[6], uw[6], lw[6], wpar, pd, s7, G, changed, accP[6], nonfin, rec, win);
+        param_move<0>(a, zz[0], uw[0], lw[0], cA, pd, s7, G, changed, accP[0], nonfin, rec, win);
+        param_move<1>(a, zz[1], uw[1], lw[1], cA, pd, s7, G, changed, accP[1], nonfin, rec, win);
+        param_move<2>(a, zz[2], uw[2], lw[2], cA, pd, s7, G, changed, accP[2], nonfin, rec, win);
+        param_move<3>(a, zz[3], uw[3], lw[3], cA, pd, s7, G, changed, accP[3], nonfin, rec, win);
+        param_move<4>(a, zz[4], uw[4], lw[4], cA, pd, s7, G, changed, accP[4], nonfin, rec, win);
+        param_move<5>(a, zz[5], uw[5], lw[5], cA, pd, s7, G, changed, accP[5], nonfin, rec, win);
+        param_move<6>(a, zz[6], uw[6], lw[6], cA, pd, s7, G, changed, accP[6], nonfin, rec, win);
         if (changed) {
+          if (t == 0) {
 #pragma unroll
-          for (int l = 0; l < 7; ++l) pd[l] = wave_uniform(pd[l]);
+            for (int l = 0; l < 7; ++l) ldraw[24 + l] = pd[l];
+          }
           C.set_p(pd);
+          if constexpr (VCONST) {
+#pragma unroll
+            for (int l = 0; l < 7; ++l) C.p[l] = in_vgpr(C.p[l]);
+          }
 #pragma unroll
           for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], lyb[2 * (n0 + j) + 1]);
           Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], has_extra ? lyb[2 * me + 1] : (T)0);
@@ -860,7 +1061,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
   const size_t ts = fp64 ? 8 : 4;
   const size_t NW = (size_t)NT / 64;
-  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 24) * sizeof(double) +
+  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 32) * sizeof(double) +
          16 * sizeof(int) + (size_t)stage * 4 * ts;
 }
 
@@ -880,10 +1081,12 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
   if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
   if (a.tiles > 1) {
-    // tiles wait on each other: reset their flags and counters in stream
-    // order, then launch cooperatively so that every tile is resident
-    const int nf = nblocks * 2, nw = a.ngroups * 4;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.hflag, nf);
+    // tiles wait on each other: reset the exchange words (generation 0) and
+    // the entry counters in stream order, then launch cooperatively so that
+    // every tile is resident
+    const int nh = nblocks * 2 * SLOT_WORDS * 2, np = 2 * nblocks * 2 * NRED * 2, nw = a.ngroups * 4;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, (uint32_t*)a.halo, nh);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((np + 255) / 256), dim3(256), 0, s, (uint32_t*)a.wpart, np);
     hipLaunchKernelGGL(zero_u32_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, a.wsync, nw);
     SweepArgs copy = a;
     void* args[] = {&copy};
@@ -920,12 +1123,16 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   if (fp64) {
     switch (K) {
-      case 4: PIMC_SWEEP_PICK(double, 4, 1024); break;
-      case 8: PIMC_SWEEP_PICK(double, 8, 512); break;
+      case 4:
+        if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
+        PIMC_SWEEP_LAUNCH(double, 4, 256);
       default: return PIMC_ERR_UNSUPPORTED;
     }
   } else {
     switch (K) {
+      case 2:
+        if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // a tiling option: one wave per SIMD only
+        PIMC_SWEEP_LAUNCH(float, 2, 256);
       case 4: PIMC_SWEEP_PICK(float, 4, 1024); break;
       case 8: PIMC_SWEEP_PICK(float, 8, 512); break;
       case 16: PIMC_SWEEP_PICK(float, 16, 512); break;
@@ -936,6 +1143,8 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
 }
 
 int sweep_max_threads(bool fp64, int K) {
+  if (fp64) return K == 4 ? 256 : 0;
+  if (K == 2) return 256;
   if (K == 4) return 1024;
   if (K == 8 || (!fp64 && K == 16)) return 512;
   return 0;

@@ -127,13 +127,17 @@ def _check_sites(gdbg, odbg, tol, margin_of):
     return int((~safe).sum())
 
 
+FP64_WIDE_OFF = pytest.mark.skip(
+    reason="FP64 windows above 1024 sites are refused: the wide FP64 shapes (more than 256 threads) spill about "
+           "1 KB per thread and the 8 x 512 shape faulted the GPU once (M = 4096) without an identified cause")
 FP64_TILES_OFF = pytest.mark.skip(
     reason="FP64 time tiles are switched off: a 16-tile FP64 window faulted the GPU once (memory aperture "
            "violation) and no cause has been shown yet; the library refuses FP64 tiled shapes")
 
 
 @pytest.mark.parametrize("M,tiles", [(1, 0), (2, 0), (8, 0), (9, 0), (37, 0), (256, 0), (300, 0), (1000, 0),
-                                     (4096, 0),
+                                     (1024, 0),
+                                     pytest.param(4096, 0, marks=FP64_WIDE_OFF),
                                      pytest.param(1000, 2, marks=FP64_TILES_OFF),
                                      pytest.param(1000, 4, marks=FP64_TILES_OFF),
                                      pytest.param(4096, 16, marks=FP64_TILES_OFF),
@@ -158,14 +162,20 @@ def test_sweep_fp64_lockstep(ctx, M, tiles):
             np.testing.assert_array_equal(gs.acc.cpu().numpy(), so.acc)
 
 
-@pytest.mark.parametrize("M,tiles", [(8, 0), (37, 0), (256, 0), (4096, 0), (8192, 0), (4096, 4), (65536, 0)])
-def test_sweep_fp32_site_parity(ctx, M, tiles):
+@pytest.mark.parametrize("M,tiles,K", [(8, 0, 0), (37, 0, 0), (256, 0, 0), (4096, 0, 0), (8192, 0, 0), (4096, 4, 0),
+                                       (65536, 0, 0), (37, 0, 2), (510, 0, 2), (4096, 8, 2), (4095, 8, 2),
+                                       (4094, 8, 2)])
+def test_sweep_fp32_site_parity(ctx, M, tiles, K):
     prob = _problem(M, dt=0.01 if M > 8192 else 0.02)
     X = _perturbed(prob, 4).astype(np.float32).astype(np.float64)
     p = prob.p_true * 0.99
     y32 = prob.y.astype(np.float32).astype(np.float64)
     I32 = prob.I.astype(np.float32).astype(np.float64)
-    win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 77, "fp32", flags=P._lib.PIMC_STATES, tiles=tiles)
+    ctx.set_tile(K)
+    try:
+        win, gd, gs = _gpu_one_sweep(ctx, prob, X, p, 77, "fp32", flags=P._lib.PIMC_STATES, tiles=tiles)
+    finally:
+        ctx.set_tile(0)
     xp = gd.xprop.cpu().numpy().astype(np.float64)
     # proposals: same Philox words, FP32 Box-Muller vs FP64
     Xo, po, od, so = _oracle_one_sweep(prob, X, p, 77, flags=OS.STATES)
@@ -265,13 +275,15 @@ def test_tiling_invariance_fp32(ctx):
     prob = _problem(1000)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     outs = []
-    for K in (4, 8, 16):
+    for K, T in ((4, 0), (8, 0), (16, 0), (2, 4)):
         ctx.set_tile(K)
+        ctx.set_tiles(T)
         win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
         P.pimc_sweep(ctx, prob.model, win, seed=9, chain=1, sweep0=0, w=w, n_sweeps=25)
         assert ctx.sync() == 0
         outs.append((win.X.cpu().numpy(), win.p.cpu().numpy()))
     ctx.set_tile(0)
+    ctx.set_tiles(0)
     for X, p in outs[1:]:
         np.testing.assert_array_equal(X, outs[0][0])
         np.testing.assert_allclose(p, outs[0][1], rtol=1e-14)
@@ -285,16 +297,18 @@ def test_time_tiles_give_the_same_chain(ctx, M):
     prob = _problem(M, dt=0.01 if M > 8192 else 0.02)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     outs = []
-    choices = (1, 2, 4, 16) if M == 4096 else (0, 32, 64)
+    choices = ((0, 1), (0, 2), (0, 4), (0, 16), (2, 8), (2, 16)) if M == 4096 else ((0, 0), (0, 32), (0, 64), (2, 128))
     n = 20 if M == 4096 else 4
-    for T in choices:
+    for K, T in choices:
+        ctx.set_tile(K)
         ctx.set_tiles(T)
         win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
         st = P.SweepStats.allocate(win, n, burn=0)
-        print(f"tiles={T} M={M}", flush=True)
+        print(f"K={K} tiles={T} M={M}", flush=True)
         P.pimc_sweep(ctx, prob.model, win, seed=21, chain=2, sweep0=5, w=w, n_sweeps=n, stats=st)
         rc = ctx.sync()
         ctx.set_tiles(0)
+        ctx.set_tile(0)
         assert rc == 0
         outs.append((win.X.cpu().numpy(), win.p.cpu().numpy(), st.acc.cpu().numpy(), st.sum.cpu().numpy(),
                      st.ptrace.cpu().numpy()))
@@ -429,6 +443,27 @@ def test_oversized_window_refused_on_host(ctx):
     assert ctx.sync() == 0
     small = P.Window.from_arrays(prob.X0[:65], prob.p0, prob.y[:65], prob.I[:65], "fp64")
     P.pimc_sweep(ctx, prob.model, small, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    assert ctx.sync() == 0
+
+
+def test_fp64_window_limit(ctx):
+    """FP64 windows run in one spill-free workgroup: M = 1024 runs, M = 1025
+    is refused on the host (nothing enqueued) for every sites-per-thread
+    setting."""
+    prob = _problem(1025, init="truth")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    ok = P.Window.from_arrays(prob.X0[:1025], prob.p0, prob.y[:1025], prob.I[:1025], "fp64")
+    P.pimc_sweep(ctx, prob.model, ok, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+    assert ctx.sync() == 0
+    big = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    for K in (0, 4, 8):
+        ctx.set_tile(K)
+        try:
+            with pytest.raises(P._lib.PimcError) as e:
+                P.pimc_sweep(ctx, prob.model, big, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1)
+        finally:
+            ctx.set_tile(0)
+        assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
     assert ctx.sync() == 0
 
 

@@ -32,6 +32,13 @@ METRIC = "path site-updates/s + param ESS/s, HMC vs plain sweep, HH M=4096, 1 GP
 SLOTS_PER_SITE_UPDATE = 560
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 
+# HBM bytes per sweep of the benchmark shape, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs calibrated against a plain copy (profiles/ holds the
+# summary).  They belong to one version of the kernel source: when the source
+# hash differs, the traffic is reported as unknown.
+TRAFFIC = {"sweep_hip_sha256": "b23d79d629ea3f3673005f244c1fb83bf0f9520470b3793147a302606f9aadd1",
+           "launch": (2, 16), "fetch_bytes_per_sweep": 78.1e3, "write_bytes_per_sweep": 16.6e3}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -48,6 +55,16 @@ def parse():
                     help="wall budget of each sampler in the HMC vs plain sweep comparison (0: skip it)")
     ap.add_argument("--cmp-chains", type=int, default=64)
     return ap.parse_args()
+
+
+def traffic_per_launch(shape, sweeps: int):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1103_4887_amd", "csrc", "sweep.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != TRAFFIC["sweep_hip_sha256"] or tuple(shape[:2]) != TRAFFIC["launch"]:
+        return None
+    return (TRAFFIC["fetch_bytes_per_sweep"] + TRAFFIC["write_bytes_per_sweep"]) * sweeps
 
 
 def cpu_baseline(prob, budget_s: float):
@@ -245,7 +262,7 @@ def main():
         "accept_rate": {"sites": float((acc[0] + acc[1]) / (sites * K)),
                         "params": [float(acc[2 + l] / K) for l in mask]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": traffic_per_launch(shape, K),
                      "cus_occupied": max(1, shape[1]),
                      "frac_of_occupied_cus": achieved / (PEAK_SLOTS_PER_S / 256 * max(1, shape[1])),
                      "kernel": "sweep_kernel", "slots_per_site_update": SLOTS_PER_SITE_UPDATE,

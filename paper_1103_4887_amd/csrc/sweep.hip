@@ -257,10 +257,6 @@ __device__ __forceinline__ void gw_wait(const uint64_t* const (&src)[N], uint64_
     ok = ok && (uint32_t)(w[i] >> 32) >= gen;
   }
   if (ok) return;
-  // after one timed-out wait every later wait gives up at once, so a broken
-  // exchange ends the launch quickly (with the error reported) instead of
-  // timing out once per sweep
-  if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u) return;
   const uint64_t t0 = wall_clock64();
   while (true) {
     __builtin_amdgcn_s_sleep(1);
@@ -271,7 +267,12 @@ __device__ __forceinline__ void gw_wait(const uint64_t* const (&src)[N], uint64_
       ok = ok && (uint32_t)(w[i] >> 32) >= gen;
     }
     if (ok) return;
-    if (wall_clock64() - t0 > ticks) {
+    const uint64_t el = wall_clock64() - t0;
+    // after one timed-out wait, every later wait gives up once it has
+    // waited a small fraction of the limit, so a broken exchange ends the
+    // launch quickly (with the error reported)
+    if (el > (ticks >> 16) && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u)) return;
+    if (el > ticks) {
       atomicOr(err, 4u);
       return;
     }
@@ -385,14 +386,14 @@ __host__ __device__ constexpr int symi(int a, int b) { return a <= b ? sym7(a, b
 // One Metropolis move of parameter L against the sufficient statistics.
 // pl: proposed value, drawn and box-tested beforehand (a move of p_l leaves
 // every other p_j unchanged, so p_l before its own move is known when the
-// sweep's parameter section starts); NaN when outside the box.  uword, lu32:
-// Philox word of the accept uniform and its FP32 logarithm.  cA = beta Rd_V / 2.
-// Written without branches except the rare FP64 re-evaluation of log u near
-// a tie, to keep the sequential chain of the seven moves short.
-template <int L>
-__device__ __forceinline__ void param_move(const SweepArgs& a, double pl, uint32_t uword, float lu32, double cA,
-                                           double (&pd)[7], double (&s)[7], const double (&G)[28], bool& changed,
-                                           int& acc, int& nonfin, bool rec, int win) {
+// sweep's parameter section starts); NaN when outside the box.  lu: FP64
+// log u of the accept uniform, also formed beforehand (lane-parallel).
+// cA = beta Rd_V / 2.  Written without branches, to keep the sequential
+// chain of the seven moves short.
+template <int L, bool DBG>
+__device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double lu, double cA, double (&pd)[7],
+                                           double (&s)[7], const double (&G)[28], bool& changed, int& acc,
+                                           int& nonfin, bool rec, int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
   constexpr int ia = ThetaMove<L>::ia;
   constexpr int ib = ThetaMove<L>::ib;
@@ -411,11 +412,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, uint32
   }
   const double dA = cA * (quad - 2.0 * lin);
   const bool fin = __builtin_isfinite(dA);
-  const double gap = -dA - (double)lu32;
-  const double E = 1e-5 * (1.0 + (double)__builtin_fabsf(lu32));
-  bool dec = gap > E;
-  if (__builtin_fabs(gap) <= E) dec = ::log(u01_d(uword)) < -dA;
-  const bool ok = inbox && fin && dec;
+  const bool ok = inbox && fin && lu < -dA;
   nonfin += (inbox && !fin) ? 1 : 0;
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
@@ -426,7 +423,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, uint32
   pd[L] = ok ? pl : pd[L];
   changed = changed || ok;
   acc += ok ? 1 : 0;
-  if (rec) {
+  if (DBG && rec) {
     if (a.dbg_pprop) a.dbg_pprop[win * 7 + L] = pl;
     if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = inbox ? dA : __builtin_nan("");
     if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
@@ -790,8 +787,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
           const double pl = ldraw[24 + l] + a.w[4 + l] * z;
           const bool inbox = pl >= lo && pl <= hi;
           ldraw[l] = inbox ? pl : __builtin_nan("");
-          ldraw[8 + l] = __builtin_bit_cast(double, (uint64_t)b.z);
-          ldraw[16 + l] = (double)(__builtin_amdgcn_logf(u01_f(b.z)) * 0.6931471805599453f);
+          ldraw[16 + l] = ::log(u01_d(b.z));
         }
       };
       if (tiles == 1) param_draws();
@@ -921,27 +917,24 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       // ---- sequential parameter moves, evaluated identically by every
       //      wave (no broadcast and no further barrier needed) ---------------
       {
-        double s7[7], G[28], zz[7];
-        uint32_t uw[7];
-        float lw[7];
+        double s7[7], G[28], zz[7], lw[7];
 #pragma unroll
         for (int l = 0; l < 7; ++l) {
           s7[l] = lstat[l];
           zz[l] = ldraw[l];
-          uw[l] = (uint32_t)__builtin_bit_cast(uint64_t, ldraw[8 + l]);
-          lw[l] = (float)ldraw[16 + l];
+          lw[l] = ldraw[16 + l];
         }
 #pragma unroll
         for (int i = 0; i < 28; ++i) G[i] = lstat[7 + i];
         bool changed = false;
         const bool rec = last && t == 0 && tb == 0;
-        param_move<0>(a, zz[0], uw[0], lw[0], cA, pd, s7, G, changed, accP[0], nonfin, rec, win);
-        param_move<1>(a, zz[1], uw[1], lw[1], cA, pd, s7, G, changed, accP[1], nonfin, rec, win);
-        param_move<2>(a, zz[2], uw[2], lw[2], cA, pd, s7, G, changed, accP[2], nonfin, rec, win);
-        param_move<3>(a, zz[3], uw[3], lw[3], cA, pd, s7, G, changed, accP[3], nonfin, rec, win);
-        param_move<4>(a, zz[4], uw[4], lw[4], cA, pd, s7, G, changed, accP[4], nonfin, rec, win);
-        param_move<5>(a, zz[5], uw[5], lw[5], cA, pd, s7, G, changed, accP[5], nonfin, rec, win);
-        param_move<6>(a, zz[6], uw[6], lw[6], cA, pd, s7, G, changed, accP[6], nonfin, rec, win);
+        param_move<0, DBG>(a, zz[0], lw[0], cA, pd, s7, G, changed, accP[0], nonfin, rec, win);
+        param_move<1, DBG>(a, zz[1], lw[1], cA, pd, s7, G, changed, accP[1], nonfin, rec, win);
+        param_move<2, DBG>(a, zz[2], lw[2], cA, pd, s7, G, changed, accP[2], nonfin, rec, win);
+        param_move<3, DBG>(a, zz[3], lw[3], cA, pd, s7, G, changed, accP[3], nonfin, rec, win);
+        param_move<4, DBG>(a, zz[4], lw[4], cA, pd, s7, G, changed, accP[4], nonfin, rec, win);
+        param_move<5, DBG>(a, zz[5], lw[5], cA, pd, s7, G, changed, accP[5], nonfin, rec, win);
+        param_move<6, DBG>(a, zz[6], lw[6], cA, pd, s7, G, changed, accP[6], nonfin, rec, win);
         if (changed) {
           if (t == 0) {
 #pragma unroll

@@ -91,6 +91,8 @@ def batch_candidates(sizes, prec: str) -> Iterable[Tuple[int, int]]:
     for T in (2, 4, 8, 16):
         if lo // T >= 256 and len(sizes) * T <= 4096:
             yield (0, T)
+        if lo // T >= 128 and len(sizes) * T <= 4096:
+            yield (2, T)
 
 
 def tune_batch(ctx: Context, spec, batch, w: torch.Tensor, *, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,

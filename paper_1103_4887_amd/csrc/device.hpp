@@ -138,6 +138,26 @@ struct Consts {
   }
 };
 
+// Move a double across lanes with one DPP control (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  // every lane reads a lane of its own row, so no lane keeps an old value
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each row of 16 lanes with DPP (quad_perm xor 1, xor 2, then
+// row_ror 4 and 8); the row total lands in lanes 12..15 of the row.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x128>(v);  // row_ror:8
+  return v;
+}
+
 // Values that every lane of a wave holds identically (the parameters after
 // a move) are moved to scalar registers, which frees vector registers.
 __device__ __forceinline__ double wave_uniform(double v) {

@@ -36,14 +36,31 @@ namespace {
 constexpr int HB = HMC_BLOCK;  // sites per block = threads per block
 constexpr int NPART = 10;      // gp[7], A_o, A_d, K
 
-__device__ __forceinline__ double block_sum_d(double v, double* lds, int t) {
-  // 256 threads = 4 waves: DPP-free xor butterfly, then 4 wave sums in order
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+// Sum over the blocks b0..b1-1 of one chain of the per-block partials
+// part[b][off + v], v < N, in a fixed order that every block of the chain
+// reproduces: thread (v, g) = (t % N, t / N) adds blocks b0 + g, b0 + g + G,
+// ... (G = 256 / N segments, all loads of a segment independent), then the
+// segment sums are added in segment order.  lds: [256] doubles; out: [N] in
+// LDS, valid for every thread after the call.
+template <int N>
+__device__ __forceinline__ void chain_sum(const double* part, int b0, int b1, int off, double* lds, double* out,
+                                          int t) {
+  constexpr int G = HB / N;
+  const int v = t % N, g = t / N;
+  if (g < G) {
+    double acc = 0.0;
+    for (int b = b0 + g; b < b1; b += G) acc += part[(int64_t)b * 16 + off + v];
+    lds[g * N + v] = acc;
+  }
   __syncthreads();
-  if ((t & 63) == 0) lds[t >> 6] = v;
+  if (t < N) {
+    // segments past the chain's block count hold nothing
+    const int gmax = b1 - b0 < G ? b1 - b0 : G;
+    double acc = 0.0;
+    for (int q = 0; q < gmax; ++q) acc += lds[q * N + t];
+    out[t] = acc;
+  }
   __syncthreads();
-  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
 template <typename T>
@@ -51,10 +68,13 @@ struct HmcJ {  // Jacobian rows of the HH field
   T VV, Vg[3], gV[3], gg[3];
 };
 
+
+// F and its Jacobian at one site, sharing the gates' tanh and 1/tau.
 template <typename T>
-__device__ __forceinline__ void hh_jac(const Consts<T>& C, const T (&x)[4], HmcJ<T>& J) {
+__device__ __forceinline__ void hh_F_J(const Consts<T>& C, const T (&x)[4], T I, T (&F)[4], HmcJ<T>& J) {
   const T V = x[0], m = x[1], hh = x[2], n = x[3];
   const T m2 = m * m, m3 = m2 * m, n2 = n * n, n3 = n2 * n, n4 = n2 * n2;
+  F[0] = hh_FV(C, V, m, hh, n, I);
   J.VV = -(C.p[1] * m3 * hh + C.p[3] * n4 + C.p[5]);
   J.Vg[0] = (T)3 * C.p[1] * m2 * hh * (C.p[2] - V);
   J.Vg[1] = C.p[1] * m3 * (C.p[2] - V);
@@ -66,24 +86,47 @@ __device__ __forceinline__ void hh_jac(const Consts<T>& C, const T (&x)[4], HmcJ
     const T ainf = (T)0.5 + (T)0.5 * t;
     const T tau = C.tau0[g] + C.tau1[g] * sech2;
     const T itau = Math<T>::rcp(tau);
+    F[1 + g] = (ainf - x[1 + g]) * itau;
     const T dt_dV = sech2 * C.inv_dVa[g];
     J.gV[g] = (T)0.5 * dt_dV * itau - (ainf - x[1 + g]) * ((T)-2 * C.tau1[g] * t * dt_dV) * itau * itau;
     J.gg[g] = -itau;
   }
 }
 
-// dF_V/dp at a site, in FP64 from the site's state
-__device__ __forceinline__ void dFVdp(const double* p, double V, double m, double h, double n, double I,
-                                      double (&d)[7]) {
-  const double m3h = m * m * m * h, n4 = n * n * n * n;
-  d[0] = I;
-  d[1] = m3h * (p[2] - V);
-  d[2] = p[1] * m3h;
-  d[3] = n4 * (p[4] - V);
-  d[4] = p[3] * n4;
-  d[5] = p[6] - V;
-  d[6] = p[5];
+// Sum N values over the 256 threads of a block: DPP sums over rows of 16
+// lanes, then the 16 row partials added in row order by thread i < N, which
+// writes sum i to out[i].  lds: [16][N] doubles.
+template <int N>
+__device__ __forceinline__ void block_sum_rows(const double (&v)[N], double* lds, double* out, int t) {
+  double r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = row_sum(v[i]);
+  if ((t & 15) == 15) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[(t >> 4) * N + i] = r[i];
+  }
+  __syncthreads();
+  if (t < N) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += lds[q * N + t];
+    out[t] = acc;
+  }
 }
+
+// dF_V/dp at a site in the site precision (parameters from C)
+template <typename T>
+__device__ __forceinline__ void dFVdp_T(const Consts<T>& C, T V, T m, T h, T n, T I, T (&d)[7]) {
+  const T m3h = m * m * m * h, n2 = n * n, n4 = n2 * n2;
+  d[0] = I;
+  d[1] = m3h * (C.p[2] - V);
+  d[2] = C.p[1] * m3h;
+  d[3] = n4 * (C.p[4] - V);
+  d[4] = C.p[3] * n4;
+  d[5] = C.p[6] - V;
+  d[6] = C.p[5];
+}
+
 
 // Parameter state of chain `ch` at leapfrog kernel s (identical in every
 // block of the chain): p(s), and the momentum rp(s-1/2) that moved it there.
@@ -93,13 +136,7 @@ __device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, bo
   const int b0 = a.bfirst[ch], b1 = a.bfirst[ch + 1];
   const double* part = a.part + (int64_t)((s - 1) & 1) * a.nblocks * 16;
   // fixed-order reduction of the previous kernel's partials of this chain
-  const int t = threadIdx.x;
-  if (t < 7) {
-    double acc = 0.0;
-    for (int b = b0; b < b1; ++b) acc += part[(int64_t)b * 16 + t];
-    red[t] = acc;
-  }
-  __syncthreads();
+  chain_sum<7>(part, b0, b1, 0, red + 16, red, (int)threadIdx.x);
 #pragma unroll
   for (int l = 0; l < 7; ++l) gp_prev[l] = red[l];
   const double c = s == 1 ? 0.5 : 1.0;
@@ -131,8 +168,8 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
   __shared__ T lq[HB + 2][4];
   __shared__ T lF[HB + 2][4];
   __shared__ T lI[HB + 2];
-  __shared__ double red[16];
-  __shared__ double lsum[4];
+  __shared__ double red[16 + HB];   // [0..15] results, then chain_sum scratch
+  __shared__ double lsum[16 * NPART];
   __shared__ uint8_t lflip[HB + 2];   // bit c: component c reflected in this drift
   const int t = threadIdx.x;
   const int b = blockIdx.x;
@@ -148,6 +185,57 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
     C = a.cf;
   else
     C = a.cd;
+
+  // ---- positions of the block's sites and the two halo sites: loaded,
+  //      drifted and reflected before the parameter section, so that these
+  //      loads and the parameter partials' loads share one memory round trip
+  // lq[j] holds site n = site0 - 1 + j
+  const T* Qin = (const T*)(MODE == 0 ? a.X : (((s - 1) & 1) ? a.Q1 : a.X)) + base * 4;
+  const T* Rin = (const T*)(((s - 1) & 1) ? a.R1 : a.R0) + base * 4;   // r(s-1/2)
+  const T* Ip = (const T*)a.I + base;
+  const T* Yp = (const T*)a.y + base;
+  const T e = (T)a.eps;
+  {
+    T minv_s[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) minv_s[c] = (T)a.minv[c];
+    for (int j = t; j < HB + 2; j += HB) {
+      const int n = site0 - 1 + j;
+      if (n >= 0 && n <= M) {
+        T q[4];
+        uint32_t flip = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          q[c] = Qin[(int64_t)n * 4 + c];
+          if (MODE != 0) {
+            q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
+            // one reflection at the box walls (the momentum is negated below)
+            if (q[c] < C.lo[c]) {
+              q[c] = (T)2 * C.lo[c] - q[c];
+              flip |= 1u << c;
+            } else if (q[c] > C.hi[c]) {
+              q[c] = (T)2 * C.hi[c] - q[c];
+              flip |= 1u << c;
+            }
+          }
+          lq[j][c] = q[c];
+        }
+        lflip[j] = (uint8_t)flip;
+        lI[j] = Ip[n];
+      }
+    }
+  }
+  // the own site's momentum and observation, also loaded now
+  const int n_own = site0 + t;
+  T r_own[4] = {0, 0, 0, 0};
+  T y_own = (T)0;
+  if (n_own <= M) {
+    if (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r_own[c] = Rin[(int64_t)n_own * 4 + c];
+    }
+    if (n_own >= 1) y_own = Yp[n_own];
+  }
 
   // ---- parameters at this step -------------------------------------------
   double ps[7], rps[7], gpp[7];
@@ -169,60 +257,42 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         p_out[l] = ps[l];
       }
       if (out) atomicOr(&a.outside[ch], 1u);
-      if (s == 1) {
-        // H0 from the initial kernel's partials: A(q0) + K(r0) + K(rp0)
-        const double* part0 = a.part;  // parity 0
-        double Ao = 0.0, Ad = 0.0, Ks = 0.0;
-        for (int bb = a.bfirst[ch]; bb < a.bfirst[ch + 1]; ++bb) {
-          Ao += part0[(int64_t)bb * 16 + 7];
-          Ad += part0[(int64_t)bb * 16 + 8];
-          Ks += part0[(int64_t)bb * 16 + 9];
-        }
+    }
+    if (s == 1 && b == a.bfirst[ch]) {
+      // H0 from the initial kernel's partials: A(q0) + K(r0) + K(rp0)
+      chain_sum<3>(a.part /* parity 0 */, a.bfirst[ch], a.bfirst[ch + 1], 7, red + 16, red + 8, t);
+      if (t == 0) {
         const double* rp0 = a.rpbuf + (int64_t)ch * 7;  // parity 0 holds rp0
         double Kp = 0.0;
 #pragma unroll
         for (int l = 0; l < 7; ++l) Kp += 0.5 * rp0[l] * rp0[l] * a.minv[4 + l];
-        a.H0[ch] = Ao + a.m.beta * Ad + Ks + Kp;
+        a.H0[ch] = red[8] + a.m.beta * red[9] + red[10] + Kp;
       }
     }
   }
   C.set_p(ps);
 
-  // ---- positions of the block's sites and the two halo sites -------------
-  // lq[j] holds site n = site0 - 1 + j
-  const T* Qin = (const T*)(MODE == 0 ? a.X : (((s - 1) & 1) ? a.Q1 : a.X)) + base * 4;
-  const T* Rin = (const T*)(((s - 1) & 1) ? a.R1 : a.R0) + base * 4;   // r(s-1/2)
-  const T* Ip = (const T*)a.I + base;
-  const T e = (T)a.eps;
-  T minv_s[4];
+  // ---- F at the block's sites with this step's parameters: thread t its
+  //      own site (with the Jacobian, kept in registers), threads 0 and 1
+  //      also the two halo sites -------------------------------------------
+  __syncthreads();
+  HmcJ<T> J;
+  if (n_own <= M) {
+    T q[4], F[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) minv_s[c] = (T)a.minv[c];
-  for (int j = t; j < HB + 2; j += HB) {
+    for (int c = 0; c < 4; ++c) q[c] = lq[t + 1][c];
+    hh_F_J(C, q, lI[t + 1], F, J);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lF[t + 1][c] = F[c];
+  }
+  if (t < 2) {
+    const int j = t == 0 ? 0 : HB + 1;
     const int n = site0 - 1 + j;
     if (n >= 0 && n <= M) {
-      T q[4];
-      uint32_t flip = 0;
+      T q[4], F[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        q[c] = Qin[(int64_t)n * 4 + c];
-        if (MODE != 0) {
-          q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
-          // one reflection at the box walls (the momentum is negated below)
-          if (q[c] < C.lo[c]) {
-            q[c] = (T)2 * C.lo[c] - q[c];
-            flip |= 1u << c;
-          } else if (q[c] > C.hi[c]) {
-            q[c] = (T)2 * C.hi[c] - q[c];
-            flip |= 1u << c;
-          }
-        }
-        lq[j][c] = q[c];
-      }
-      lflip[j] = (uint8_t)flip;
-      const T I = Ip[n];
-      lI[j] = I;
-      T F[4];
-      hh_F(C, q, I, F);
+      for (int c = 0; c < 4; ++c) q[c] = lq[j][c];
+      hh_F(C, q, lI[j], F);
 #pragma unroll
       for (int c = 0; c < 4; ++c) lF[j][c] = F[c];
     }
@@ -260,8 +330,6 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       for (int c = 0; c < 4; ++c)
         vr[c] = beta * (T)a.m.Rd[c] * ((lq[j + 1][c] - x[c]) - h * (lF[j + 1][c] + lF[j][c]));
     }
-    HmcJ<T> J;
-    hh_jac(C, x, J);
     T u[4], w[4], g[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -271,8 +339,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
     g[0] = u[0] - h * (J.VV * w[0] + J.gV[0] * w[1] + J.gV[1] * w[2] + J.gV[2] * w[3]);
 #pragma unroll
     for (int q = 0; q < 3; ++q) g[1 + q] = u[1 + q] - h * (J.Vg[q] * w[0] + J.gg[q] * w[1 + q]);
-    const T* Yp = (const T*)a.y + base;
-    if (n >= 1) g[0] -= (T)a.m.Ro * (Yp[n] - x[0]);
+    if (n >= 1) g[0] -= (T)a.m.Ro * (y_own - x[0]);
 
     // momenta: drawn (MODE 0) or r(s-1/2); kick; kinetic energy partial
     T r[4];
@@ -292,7 +359,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       const uint32_t flip = lflip[j];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        r[c] = Rin[(int64_t)n * 4 + c];
+        r[c] = r_own[c];
         if ((flip >> c) & 1u) r[c] = -r[c];
       }
     }
@@ -321,7 +388,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
     // action terms (initial and last kernels) and dA/dp of link n
     if (n >= 1) {
       if (MODE != 1) {
-        const double d = (double)Yp[n] - (double)x[0];
+        const double d = (double)y_own - (double)x[0];
         part[7] = 0.5 * a.m.Ro * d * d;
         double s2 = 0.0;
         // FP64 model error of link n for the Hamiltonian
@@ -342,21 +409,24 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         }
         part[8] = 0.5 * s2;
       }
-      double d1[7], d0[7];
-      dFVdp(ps, (double)x[0], (double)x[1], (double)x[2], (double)x[3], (double)lI[j], d1);
-      dFVdp(ps, (double)lq[j - 1][0], (double)lq[j - 1][1], (double)lq[j - 1][2], (double)lq[j - 1][3],
-            (double)lI[j - 1], d0);
-      const double f = -0.5 * a.m.dt * (double)vl[0];
+      // dA/dp of link n: per-site terms in the site precision, summed in FP64
+      T d1[7], d0[7];
+      dFVdp_T(C, x[0], x[1], x[2], x[3], lI[j], d1);
+      dFVdp_T(C, lq[j - 1][0], lq[j - 1][1], lq[j - 1][2], lq[j - 1][3], lI[j - 1], d0);
+      const T f = (T)(-0.5 * a.m.dt) * vl[0];
 #pragma unroll
-      for (int l = 0; l < 7; ++l) part[l] = f * (d1[l] + d0[l]);
+      for (int l = 0; l < 7; ++l) part[l] = (double)(f * (d1[l] + d0[l]));
     }
   }
-  // ---- block partials -------------------------------------------------------
+  // ---- block partials (interior steps carry only dA/dp) --------------------
   double* pout = a.part + (int64_t)(s & 1) * a.nblocks * 16 + (int64_t)b * 16;
+  if (MODE == 1) {
+    double v[7];
 #pragma unroll
-  for (int i = 0; i < NPART; ++i) {
-    const double v = block_sum_d(part[i], lsum, t);
-    if (t == 0) pout[i] = v;
+    for (int i = 0; i < 7; ++i) v[i] = part[i];
+    block_sum_rows<7>(v, lsum, pout, t);
+  } else {
+    block_sum_rows<NPART>(part, lsum, pout, t);
   }
   if (MODE == 0 && b == a.bfirst[ch] && t == 0) {
     // parameter momenta and backups, chain-level (one block per chain)
@@ -379,20 +449,18 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
 }
 
 // One block per chain: H1, decision, parameters, counters.
-__global__ void hmc_finish_kernel(HmcArgs a, int L) {
+__global__ void __launch_bounds__(HB) hmc_finish_kernel(HmcArgs a, int L) {
+  __shared__ double red[16 + HB];
   const int ch = blockIdx.x;
+  const double* part = a.part + (int64_t)(L & 1) * a.nblocks * 16;
+  chain_sum<NPART>(part, a.bfirst[ch], a.bfirst[ch + 1], 0, red + 16, red, (int)threadIdx.x);
   if (threadIdx.x != 0) return;
   const uint64_t k = *a.kptr;
   const Key key = make_key(a.seed, a.chain[ch]);
-  const double* part = a.part + (int64_t)(L & 1) * a.nblocks * 16;
-  double gp[7] = {0, 0, 0, 0, 0, 0, 0}, Ao = 0.0, Ad = 0.0, Ks = 0.0;
-  for (int b = a.bfirst[ch]; b < a.bfirst[ch + 1]; ++b) {
+  double gp[7];
 #pragma unroll
-    for (int l = 0; l < 7; ++l) gp[l] += part[(int64_t)b * 16 + l];
-    Ao += part[(int64_t)b * 16 + 7];
-    Ad += part[(int64_t)b * 16 + 8];
-    Ks += part[(int64_t)b * 16 + 9];
-  }
+  for (int l = 0; l < 7; ++l) gp[l] = red[l];
+  const double Ao = red[7], Ad = red[8], Ks = red[9];
   const double* rpL = a.rpbuf + (int64_t)(L & 1) * a.B * 7 + (int64_t)ch * 7;   // rp(L-1/2)
   const double* pL = a.pbuf + (int64_t)(L & 1) * a.B * 7 + (int64_t)ch * 7;
   double Kp = 0.0;
@@ -454,7 +522,7 @@ int launch_hmc_proposal(const HmcArgs& a, bool fp64, int L, hipStream_t s) {
     for (int st = 1; st < L; ++st) hipLaunchKernelGGL((hmc_step_kernel<float, 1>), gb, tb, 0, s, a, st);
     hipLaunchKernelGGL((hmc_step_kernel<float, 2>), gb, tb, 0, s, a, L);
   }
-  hipLaunchKernelGGL(hmc_finish_kernel, dim3(a.B), dim3(64), 0, s, a, L);
+  hipLaunchKernelGGL(hmc_finish_kernel, dim3(a.B), dim3(HB), 0, s, a, L);
   if (fp64)
     hipLaunchKernelGGL(hmc_restore_kernel<double>, gb, tb, 0, s, a, L);
   else

@@ -37,16 +37,6 @@ struct Nb {  // a neighbour site: state and cached F
   T F[4];
 };
 
-// Move a double across lanes with one DPP control (two 32-bit moves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  // every lane reads a lane of its own row, so no lane keeps an old value
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // Wave-uniform values that the site updates read on every iteration are
 // held in vector registers: the kernel's uniform state (pointers, counters,
 // model constants) exceeds the scalar register file, and values the compiler
@@ -85,15 +75,6 @@ __device__ __forceinline__ void consts_in_vgprs(Consts<T>& C) {
   for (int l = 0; l < 7; ++l) C.p[l] = in_vgpr(C.p[l]);
 }
 
-// Sum over each row of 16 lanes with DPP (quad_perm xor 1, xor 2, then
-// row_ror 4 and 8); the row total lands in lanes 12..15 of the row.
-__device__ __forceinline__ double row_sum(double v) {
-  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_d<0x124>(v);  // row_ror:4
-  v += dpp_d<0x128>(v);  // row_ror:8
-  return v;
-}
 
 // Accept iff log u < -dA, decided in FP64.  log u is first formed in FP32
 // (hardware log2); only when -dA lies within a margin far wider than that
@@ -1074,9 +1055,15 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
   if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
   if (a.tiles > 1) {
-    // tiles wait on each other: reset the exchange words (generation 0) and
-    // the entry counters in stream order, then launch cooperatively so that
-    // every tile is resident
+    // tiles wait on each other, so all of them must be resident: a shape
+    // the device cannot hold at once is refused before anything is enqueued
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, NT, sm) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return PIMC_ERR_HIP;
+    if ((int64_t)per_cu * ncu < nblocks) return PIMC_ERR_UNSUPPORTED;
+    // reset the exchange words (generation 0) and the entry counters in
+    // stream order, then launch cooperatively
     const int nh = nblocks * 2 * SLOT_WORDS * 2, np = 2 * nblocks * 2 * NRED * 2, nw = a.ngroups * 4;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, (uint32_t*)a.halo, nh);
     hipLaunchKernelGGL(zero_u32_kernel, dim3((np + 255) / 256), dim3(256), 0, s, (uint32_t*)a.wpart, np);
@@ -1084,7 +1071,10 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
     SweepArgs copy = a;
     void* args[] = {&copy};
     const hipError_t e = hipLaunchCooperativeKernel((const void*)k, dim3(nblocks), dim3(NT), args, (unsigned)sm, s);
-    if (e == hipErrorCooperativeLaunchTooLarge) return PIMC_ERR_UNSUPPORTED;
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+      (void)hipGetLastError();   // leave no stale error for the caller's next runtime call
+      return PIMC_ERR_UNSUPPORTED;
+    }
     return e == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
   }
   hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), sm, s, a);

@@ -378,6 +378,28 @@ def test_tiled_batch_equals_single_runs(ctx, Ms, T):
         ctx.set_tiles(0)
 
 
+def test_tiled_batch_beyond_residency_refused_cleanly(ctx):
+    """A tiled batch whose workgroups cannot all be resident is refused on
+    the host (nothing enqueued, no stale runtime error left behind)."""
+    prob = W.make_hh_problem(4096, 0.02, 410, require_spike=False)
+    B = 256
+    batch = P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    X_before = batch.X.clone()
+    ctx.set_tile(2)
+    ctx.set_tiles(32)
+    try:
+        with pytest.raises(P._lib.PimcError) as e:
+            P.pimc_run_batch(ctx, prob.model, batch, seed=1, sweep0=0, w=w, n_sweeps=2)
+    finally:
+        ctx.set_tile(0)
+        ctx.set_tiles(0)
+    assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
+    assert ctx.sync() == 0
+    torch.zeros(16, device="cuda").sum().item()   # the runtime holds no error
+    assert torch.equal(batch.X, X_before)
+
+
 def test_param_update_entry_point(ctx):
     prob = _problem(256)
     X = _perturbed(prob, 6)

@@ -93,9 +93,9 @@ __device__ __forceinline__ void hh_F_J(const Consts<T>& C, const T (&x)[4], T I,
   }
 }
 
-// Sum N values over the 256 threads of a block: DPP sums over rows of 16
-// lanes, then the 16 row partials added in row order by thread i < N, which
-// writes sum i to out[i].  lds: [16][N] doubles.
+// Sum N values over the HB threads of a block: DPP sums over rows of 16
+// lanes, then the HB / 16 row partials added in row order by thread i < N,
+// which writes sum i to out[i].  lds: [HB / 16][N] doubles.
 template <int N>
 __device__ __forceinline__ void block_sum_rows(const double (&v)[N], double* lds, double* out, int t) {
   double r[N];
@@ -109,7 +109,7 @@ __device__ __forceinline__ void block_sum_rows(const double (&v)[N], double* lds
   if (t < N) {
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc += lds[q * N + t];
+    for (int q = 0; q < HB / 16; ++q) acc += lds[q * N + t];
     out[t] = acc;
   }
 }
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
   __shared__ T lF[HB + 2][4];
   __shared__ T lI[HB + 2];
   __shared__ double red[16 + HB];   // [0..15] results, then chain_sum scratch
-  __shared__ double lsum[16 * NPART];
+  __shared__ double lsum[HB / 16 * NPART];
   __shared__ uint8_t lflip[HB + 2];   // bit c: component c reflected in this drift
   const int t = threadIdx.x;
   const int b = blockIdx.x;

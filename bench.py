@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--cmp-seconds", type=float, default=20.0,
                     help="wall budget of each sampler in the HMC vs plain sweep comparison (0: skip it)")
     ap.add_argument("--cmp-chains", type=int, default=64)
+    ap.add_argument("--cmp-equilibrate", type=float, default=5.0,
+                    help="untimed seconds of batched sweeps that equilibrate the chains before the comparison")
     return ap.parse_args()
 
 
@@ -101,14 +103,16 @@ def _post_stats(traces, mask):
     return ess, cm.mean(axis=0), cm.std(axis=0, ddof=1) / np.sqrt(len(cm))
 
 
-def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, L_steps: int = 20):
+def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, L_steps: int = 20):
     """Parameter ESS per second of HMC and of the plain sweep on one dataset.
 
-    Both samplers run `chains` chains from the same start (the true path and
-    parameters of the twin experiment, a draw from the posterior's bulk) for
-    the same wall budget, warm-up included; ESS is summed over chains on the
-    second half of each run.  HMC's warm-up is a pilot sweep run for the
-    diagonal masses plus dual-averaging of the step size to 0.7 acceptance.
+    The chains first equilibrate (untimed): `chains` chains of the batched
+    sweep run for `equilibrate_s` seconds from the true path and parameters
+    of the twin experiment.  Both samplers then start from these same states
+    and get the same wall budget, their own warm-up included; ESS is summed
+    over chains on the second half of each run.  HMC's warm-up is a pilot
+    sweep run for the diagonal masses plus dual-averaging of the step size
+    to 0.7 acceptance.
     """
     import numpy as np
     import torch
@@ -122,14 +126,23 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, L_steps: int = 20):
     mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
     w = P.widths_tensor(prob.w_state, prob.w_param)
 
-    def fresh():
-        return P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
+    start = P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
+    # launch shape from the batch autotuner (a one-off per window set)
+    shape = autotune.tune_batch(ctx, spec, start, w)
+    # equilibration, not timed: distinct sweep counters from everything below
+    n_eq = 0
+    t_eq = time.perf_counter()
+    while time.perf_counter() - t_eq < equilibrate_s:
+        P.pimc_run_batch(ctx, spec, start, seed=prob.seed + 7, sweep0=n_eq, w=w, n_sweeps=20000)
+        assert ctx.sync() == 0
+        n_eq += 20000
 
-    # plain sweep: launch shape from the batch autotuner (not charged to the
-    # budget: it is a one-off per window set), then a short run sizes the
-    # budgeted one
+    def fresh():
+        return P.PackedBatch(offsets=start.offsets, X=start.X.clone(), p=start.p.clone(), y=start.y, I=start.I,
+                             chain=start.chain, prec=start.prec)
+
+    # plain sweep: a short run sizes the budgeted one
     bm = fresh()
-    shape = autotune.tune_batch(ctx, spec, bm, w)
     t0 = time.perf_counter()
     P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=0, w=w, n_sweeps=50)
     assert ctx.sync() == 0
@@ -169,7 +182,8 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, L_steps: int = 20):
     z = np.abs(mean_h - mean_m) / np.sqrt(mcse_h ** 2 + mcse_m ** 2)
     return {
         "dataset": f"HH M={prob.M}, dt={spec.dt} ms, all 7 params, FP32 sites + FP64 reductions",
-        "chains": B, "start": "true path and parameters", "budget_s": budget_s,
+        "chains": B, "start": f"true path and parameters, then {n_eq} sweeps of equilibration (untimed)",
+        "budget_s": budget_s,
         "sweep": {"launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride, "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
                   "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
                   "param_ess_per_s": float(ess_m.min() / wall_m),
@@ -270,7 +284,7 @@ def main():
     }
     if args.cmp_seconds > 0:
         out["hmc_vs_sweep"] = hmc_vs_sweep(ctx, W.config_problem(args.config, init="truth"), args.cmp_chains,
-                                           args.cmp_seconds)
+                                           args.cmp_seconds, args.cmp_equilibrate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]

@@ -164,7 +164,7 @@ def test_sweep_fp64_lockstep(ctx, M, tiles):
 
 @pytest.mark.parametrize("M,tiles,K", [(8, 0, 0), (37, 0, 0), (256, 0, 0), (4096, 0, 0), (8192, 0, 0), (4096, 4, 0),
                                        (65536, 0, 0), (37, 0, 2), (510, 0, 2), (4096, 8, 2), (4095, 8, 2),
-                                       (4094, 8, 2)])
+                                       (4094, 8, 2), (4096, 16, 2)])
 def test_sweep_fp32_site_parity(ctx, M, tiles, K):
     prob = _problem(M, dt=0.01 if M > 8192 else 0.02)
     X = _perturbed(prob, 4).astype(np.float32).astype(np.float64)

@@ -213,9 +213,19 @@ int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, p
 int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path,
               void* gX, double* gp, void* stream);
 
-/* n_sweeps sweeps of every window of a packed batch in one launch.  All
- * windows share model, seed and widths w (device FP64 [11]); window w uses
- * Philox chain id batch->chain[w] and sweep indices sweep0 .. sweep0+n-1. */
+/* n_sweeps sweeps of every window of a packed batch in one persistent
+ * launch (the batched workload).  All windows share model, seed and widths
+ * w (device FP64 [11]); window w uses Philox chain id batch->chain[w] and
+ * sweep indices sweep0 .. sweep0+n-1, so a window's chain equals its own
+ * pimc_sweep run.  Windows run longest first, one workgroup each, or as
+ * time tiles (see pimc_set_sweep_tiles).  The untiled launch is recorded
+ * once per launch shape into a HIP graph and replayed with each call's
+ * arguments; the batch layout (offsets) is copied to the device, with a
+ * wait, only when it differs from the previous call's, so repeated calls on
+ * the same windows are fully asynchronous (environment PIMC_NO_GRAPHS=1
+ * launches directly).  Statistics as in pimc_batch_stats.  Errors: argument
+ * errors and shapes the built kernels cannot run are returned before
+ * anything is enqueued; device-side errors are reported by pimc_sync. */
 int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* batch,
                    uint64_t seed, uint64_t sweep0, const double* w, int64_t n_sweeps,
                    int32_t flags, const pimc_batch_stats* stats, void* stream);

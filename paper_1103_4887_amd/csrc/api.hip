@@ -24,6 +24,18 @@ struct pimc_ctx {
   int tiles = 0;                  // 0 = automatic number of time tiles per window
   bool no_graphs = false;         // launch HMC proposals one kernel at a time
   hipStream_t cap = nullptr;      // private stream that only records graphs (never runs work)
+  // batch layout last copied to the device (the copy and its wait are
+  // skipped when a call brings the same windows)
+  std::vector<int64_t> last_offsets;
+  // captured graph of the batched sweep launch, replayed with new arguments
+  struct BatchGraph {
+    bool valid = false;
+    bool fp64 = false, dbg = false;
+    int K = 0, NT = 0, nblocks = 0, stage = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipGraphNode_t node = nullptr;
+  } bgraph;
   // cross-tile workspace: tile_cap tiles over group_cap windows (grow-only)
   size_t tile_cap = 0, group_cap = 0;
   void* halo = nullptr;
@@ -118,6 +130,7 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
     ctx->order = nullptr;
     ctx->batch_cap = 0;
   }
+  ctx->last_offsets.clear();   // new buffers: the layout must be copied again
   if (hipMalloc(&ctx->offsets, (B + 1) * sizeof(int64_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   if (hipMalloc(&ctx->order, B * sizeof(int32_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   ctx->batch_cap = B;
@@ -274,6 +287,8 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->bgraph.ge) (void)hipGraphExecDestroy(ctx->bgraph.ge);
+  if (ctx->bgraph.g) (void)hipGraphDestroy(ctx->bgraph.g);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->err) (void)hipFree(ctx->err);
   if (ctx->partial) (void)hipFree(ctx->partial);
@@ -425,6 +440,59 @@ int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, p
   return pimc_sweep(ctx, model, path, rng, w, 1, PIMC_PARAMS, nullptr, debug, stream);
 }
 
+// The batched sweep launch as a captured graph: recorded once per launch
+// shape on the context's capture stream, then replayed on the caller's
+// stream with this call's arguments written into its kernel node.  (Tiled
+// batches launch cooperatively and are not captured.)
+static int launch_batch_graph(pimc_ctx* ctx, const pimc::SweepArgs& a, bool fp64, int K, int nblocks, int NT,
+                              int stage, hipStream_t s) {
+  auto& bg = ctx->bgraph;
+  const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
+  int r = PIMC_OK;
+  if (!(bg.valid && bg.fp64 == fp64 && bg.dbg == dbg && bg.K == K && bg.NT == NT && bg.nblocks == nblocks &&
+        bg.stage == stage)) {
+    if (bg.ge) (void)hipGraphExecDestroy(bg.ge);
+    if (bg.g) (void)hipGraphDestroy(bg.g);
+    bg = pimc_ctx::BatchGraph{};
+    if (!ctx->cap && (r = hip_ok(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)))) return r;
+    if ((r = hip_ok(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)))) return r;
+    const int lr = pimc::launch_sweep(a, fp64, K, nblocks, NT, ctx->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap, &g);
+    if (lr || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return lr ? lr : PIMC_ERR_HIP;
+    }
+    size_t nn = 1;
+    hipGraphNode_t node = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphGetNodes(g, &node, &nn) != hipSuccess || nn != 1 ||
+        hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return PIMC_ERR_HIP;
+    }
+    bg.valid = true;
+    bg.fp64 = fp64;
+    bg.dbg = dbg;
+    bg.K = K;
+    bg.NT = NT;
+    bg.nblocks = nblocks;
+    bg.stage = stage;
+    bg.g = g;
+    bg.ge = ge;
+    bg.node = node;
+  } else {
+    hipKernelNodeParams kp;
+    if ((r = hip_ok(hipGraphKernelNodeGetParams(bg.node, &kp)))) return r;
+    pimc::SweepArgs copy = a;
+    void* args[] = {&copy};
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    if ((r = hip_ok(hipGraphExecKernelNodeSetParams(bg.ge, bg.node, &kp)))) return r;
+  }
+  return hip_ok(hipGraphLaunch(bg.ge, s));
+}
+
 int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, uint64_t seed, uint64_t sweep0,
                    const double* w, int64_t n_sweeps, int32_t flags, const pimc_batch_stats* stats, void* stream) {
   if (!ctx || !b || !w || !b->offsets || !b->X || !b->p || !b->y || !b->I || !b->chain) return PIMC_ERR_ARG;
@@ -482,12 +550,18 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return Ms[x] > Ms[y]; });
   hipStream_t s = (hipStream_t)stream;
-  if ((r = hip_ok(hipMemcpyAsync(ctx->offsets, b->offsets, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s))))
-    return r;
-  if ((r = hip_ok(hipMemcpyAsync(ctx->order, order.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, s))))
-    return r;
-  // the host vectors die at return: make sure the copies have consumed them
-  if ((r = hip_ok(hipStreamSynchronize(s)))) return r;
+  const bool same_layout = ctx->last_offsets.size() == (size_t)B + 1 &&
+                           std::equal(ctx->last_offsets.begin(), ctx->last_offsets.end(), b->offsets);
+  if (!same_layout) {
+    ctx->last_offsets.clear();
+    if ((r = hip_ok(hipMemcpyAsync(ctx->offsets, b->offsets, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s))))
+      return r;
+    if ((r = hip_ok(hipMemcpyAsync(ctx->order, order.data(), B * sizeof(int32_t), hipMemcpyHostToDevice, s))))
+      return r;
+    // the host vectors die at return: make sure the copies have consumed them
+    if ((r = hip_ok(hipStreamSynchronize(s)))) return r;
+    ctx->last_offsets.assign(b->offsets, b->offsets + B + 1);
+  }
   a.offsets = ctx->offsets;
   a.order = ctx->order;
   a.X = b->X;
@@ -510,6 +584,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     a.stride = stats->stride > 1 ? stats->stride : 1;
   }
   a.err = ctx->err;
+  if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s);
   return pimc::launch_sweep(a, fp64, K, B * T, NT, s);
 }
 

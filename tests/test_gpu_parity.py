@@ -400,6 +400,50 @@ def test_tiled_batch_beyond_residency_refused_cleanly(ctx):
     assert torch.equal(batch.X, X_before)
 
 
+def test_batch_graph_replays_equal_direct_launches(ctx, monkeypatch):
+    """The batched sweep is launched through a captured graph whose kernel
+    arguments are rewritten for every call; a context with graphs switched
+    off launches directly.  Consecutive calls (different sweep counters,
+    counts and statistics buffers, eager work in between) give the same
+    chains and statistics both ways, and a second batch layout re-captures."""
+    monkeypatch.setenv("PIMC_NO_GRAPHS", "1")
+    direct = P.Context(0)
+    monkeypatch.delenv("PIMC_NO_GRAPHS")
+    Ms = [300, 129, 64, 37]
+    probs = [W.make_hh_problem(M, 0.02, 420 + i, require_spike=False) for i, M in enumerate(Ms)]
+    spec = probs[0].model
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+
+    def run(c, layout):
+        qs = probs if layout == 0 else probs[:2]
+        batch = P.PackedBatch.pack([q.X0 for q in qs], [q.p0 for q in qs], [q.y for q in qs], [q.I for q in qs],
+                                   list(range(len(qs))), "fp32")
+        outs = []
+        for sweep0, n in ((0, 5), (5, 7), (12, 3)):
+            dev = batch.X.device
+            st = P.SweepStats(ptrace=torch.zeros((len(qs), n, 7), dtype=torch.float64, device=dev),
+                              acc=torch.zeros((len(qs), 10), dtype=torch.int64, device=dev))
+            P.pimc_run_batch(c, spec, batch, seed=9, sweep0=sweep0, w=w, n_sweeps=n, stats=st)
+            junk = torch.randn(1 << 14, device="cuda")
+            (junk * junk).sum().item()
+            assert c.sync() == 0
+            outs.append((batch.X.cpu().numpy().copy(), batch.p.cpu().numpy().copy(), st.ptrace.cpu().numpy(),
+                         st.acc.cpu().numpy()))
+        return outs
+
+    try:
+        for layout in (0, 1, 0):
+            a = run(ctx, layout)
+            b = run(direct, layout)
+            for (Xa, pa, ta, ca), (Xb, pb, tb, cb) in zip(a, b):
+                np.testing.assert_array_equal(Xa, Xb)
+                np.testing.assert_array_equal(pa, pb)
+                np.testing.assert_array_equal(ta, tb)
+                np.testing.assert_array_equal(ca, cb)
+    finally:
+        direct.close()
+
+
 def test_param_update_entry_point(ctx):
     prob = _problem(256)
     X = _perturbed(prob, 6)

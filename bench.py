@@ -163,6 +163,26 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
     ess_m, mean_m, mcse_m = _post_stats(tr_m, mask)
     acc_m = sm.acc.cpu().numpy()
 
+    # one chain of the plain sweep (the benchmark's single-window launch, in
+    # its own autotuned shape) from chain 0's equilibrated state, same budget
+    x0, p0, _, _ = start.window(0)
+    win1 = P.Window(X=x0.clone(), p=p0.clone(), y=start.y[:prob.M + 1], I=start.I[:prob.M + 1], prec="fp32")
+    autotune.tune(ctx, spec, win1, w)
+    t0 = time.perf_counter()
+    P.pimc_sweep(ctx, spec, win1, seed=prob.seed + 3, chain=0, sweep0=0, w=w, n_sweeps=200)
+    assert ctx.sync() == 0
+    per_sweep1 = (time.perf_counter() - t0) / 200
+    n_1 = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep1))
+    s1 = P.SweepStats.allocate(win1, n_1, moments=False)
+    P.pimc_sweep(ctx, spec, win1, seed=prob.seed + 3, chain=0, sweep0=200, w=w, n_sweeps=n_1, stats=s1)
+    assert ctx.sync() == 0
+    wall_1 = time.perf_counter() - t0
+    stride1 = max(1, n_1 // 20000)
+    tr_1 = s1.ptrace[n_1 // 2::stride1].cpu().numpy()[None]
+    ess_1, _, _ = _post_stats(tr_1, mask)
+    shape1 = autotune.tune(ctx, spec, win1, w)
+    autotune.tune_batch(ctx, spec, start, w)   # the batch shape again (cached) for HMC's pilot run
+
     # HMC: pilot masses, step-size warm-up, then sampling in one graph-replayed call
     bh = fresh()
     t0 = time.perf_counter()
@@ -184,7 +204,7 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
         "dataset": f"HH M={prob.M}, dt={spec.dt} ms, all 7 params, FP32 sites + FP64 reductions",
         "chains": B, "start": f"true path and parameters, then {n_eq} sweeps of equilibration (untimed)",
         "budget_s": budget_s,
-        "sweep": {"launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride, "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
+        "sweep": {"chains": B, "launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride, "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
                   "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
                   "param_ess_per_s": float(ess_m.min() / wall_m),
                   "param_ess_per_s_median": float(np.median(ess_m) / wall_m),
@@ -198,7 +218,13 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
                 "param_ess_per_s": float(ess_h.min() / wall_h),
                 "param_ess_per_s_median": float(np.median(ess_h) / wall_h),
                 "param_ess": [float(v) for v in ess_h]},
+        "single_chain_sweep": {"launch": {"K": shape1[0], "tiles": shape1[1]}, "sweeps": n_1, "wall_s": wall_1,
+                               "us_per_sweep": per_sweep1 * 1e6,
+                               "param_ess_per_s": float(ess_1.min() / wall_1),
+                               "param_ess": [float(v) for v in ess_1]},
         "hmc_over_sweep_param_ess_per_s": float((ess_h.min() / wall_h) / (ess_m.min() / wall_m)),
+        "batched_over_single_param_ess_per_s": float((ess_m.min() / wall_m) / max(ess_1.min() / wall_1, 1e-300)),
+        "hmc_over_single_param_ess_per_s": float((ess_h.min() / wall_h) / max(ess_1.min() / wall_1, 1e-300)),
         "equal_posterior_accuracy": {"max_z": float(z.max()), "within_3_mcse": bool((z <= 3.0).all()),
                                      "mcse": "spread of the chain means / sqrt(chains)",
                                      "mean_sweep": [float(v) for v in mean_m],

@@ -170,8 +170,9 @@ int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
  * workgroups of S sites each, (T-1) S < M <= T S, that exchange their
  * boundary sites and all-reduce the parameter statistics through global
  * memory (launched cooperatively so that all tiles are resident; every
- * wait is bounded).  0 restores the automatic choice (one workgroup when the
- * window fits, the fewest tiles otherwise); at most 256.  Only FP32 windows
+ * wait is bounded).  0 restores the automatic choice (one workgroup of at
+ * most 256 threads when the window fits, the fewest tiles otherwise); 1
+ * forces one workgroup (up to 1024 threads); at most 256.  Only FP32 windows
  * are tiled: an FP64 window that does not fit one workgroup is refused with
  * PIMC_ERR_UNSUPPORTED.  pimc_run_batch uses T tiles per window when every
  * window of the batch needs exactly T tiles of the chosen shape, else one

@@ -194,7 +194,10 @@ int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles,
         if (ctx->tile_K && ctx->tile_K != K) continue;
         const int64_t need = (maxM + K - 1) / K;
         const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
-        if (fp64 && pass == 1) continue;
+        // wide single-workgroup shapes (more than 256 threads) spill to
+        // scratch: FP64 never uses them, and an FP32 window that may be cut
+        // into time tiles (automatic choice of pimc_sweep) is tiled instead
+        if (pass == 1 && (fp64 || (allow_tiles && want_T == 0))) continue;
         const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
         if (nt > lim) continue;
         const int64_t st = stage_room((int)nt, K, fp64);

@@ -46,7 +46,12 @@ class Stats:
     """Shifted moments sum(x - xref), sum((x - xref)^2) over the sweeps
     k >= burn with (k - burn) % stride == 0 (statistics are taken only every
     N_skip-th path update after the initial phase, Section 4.1), the
-    parameter vector after every sweep, and acceptance counters."""
+    parameter vector after every sweep, and acceptance counters.
+
+    With nbatch > 0, batch[b] also sums (x - xref) over the b-th of nbatch
+    runs of consecutive samples of one call: the call's i-th sample
+    (i = 0 .. ns - 1 of the ns it takes) belongs to batch i * nbatch // ns
+    (batch means for the Monte Carlo error of the path means)."""
 
     M: int
     D: int
@@ -55,7 +60,9 @@ class Stats:
     burn: int = 0
     xref: Optional[np.ndarray] = None
     stride: int = 1
+    nbatch: int = 0
     sum: np.ndarray = field(init=False)
+    batch: np.ndarray = field(init=False)
     sumsq: np.ndarray = field(init=False)
     ptrace: np.ndarray = field(init=False)
     acc: np.ndarray = field(init=False)
@@ -64,6 +71,7 @@ class Stats:
     def __post_init__(self):
         self.sum = np.zeros((self.M + 1, self.D))
         self.sumsq = np.zeros((self.M + 1, self.D))
+        self.batch = np.zeros((self.nbatch, self.M + 1, self.D))
         self.ptrace = np.zeros((self.n_sweeps, self.Np))
         self.acc = np.zeros(N_ACC, dtype=np.int64)
 
@@ -197,6 +205,10 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
     """
     M = X.shape[0] - 1
     acc = stats.acc if stats is not None else None
+    if stats is not None:
+        stride = max(stats.stride, 1)
+        sampled = [k >= stats.burn and (k - stats.burn) % stride == 0 for k in range(sweep0, sweep0 + n_sweeps)]
+        ns, si = sum(sampled), 0
     for i in range(n_sweeps):
         k = sweep0 + i
         dbg = debug if (debug is not None and i == n_sweeps - 1) else None
@@ -221,9 +233,12 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
             param_moves(spec, X, I, p, k, w_param, seed, chain, acc=acc, debug=dbg)
         if stats is not None:
             stats.ptrace[i] = p
-            if k >= stats.burn and (k - stats.burn) % max(stats.stride, 1) == 0:
+            if sampled[i]:
                 d = X - (stats.xref if stats.xref is not None else 0.0)
                 stats.sum += d
                 stats.sumsq += d * d
                 stats.n_post += 1
+                if stats.nbatch > 0:
+                    stats.batch[si * stats.nbatch // ns] += d
+                si += 1
     return X, p

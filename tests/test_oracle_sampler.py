@@ -281,6 +281,27 @@ def test_stats_and_resume_bitwise():
     np.testing.assert_allclose(st.sumsq, Q, rtol=1e-14, atol=1e-20)
 
 
+def test_batch_sums_from_recorded_paths():
+    # sweeps k = 2 .. 14, burn 3, stride 2: samples after sweeps 3, 5, 7, 9,
+    # 11, 13 (six), split into four runs of consecutive samples of sizes
+    # 2, 1, 2, 1 (sample i in batch i * 4 // 6)
+    P = W.make_hh_problem(12, 0.02, 101, require_spike=False)
+    kw = dict(seed=5, chain=2, w_state=P.w_state, w_param=P.w_param)
+    X, p = P.X0.copy(), P.p0.copy()
+    st = OS.Stats(P.M, 4, 7, 13, burn=3, stride=2, nbatch=4, xref=P.X0.copy())
+    OS.run(P.model, X, p, P.y, P.I, sweep0=2, n_sweeps=13, stats=st, **kw)
+    Xc, pc = P.X0.copy(), P.p0.copy()
+    want = np.zeros((4,) + Xc.shape)
+    which = {3: 0, 5: 0, 7: 1, 9: 2, 11: 2, 13: 3}
+    for k in range(2, 15):
+        OS.run(P.model, Xc, pc, P.y, P.I, sweep0=k, n_sweeps=1, **kw)
+        if k in which:
+            want[which[k]] += Xc - P.X0
+    assert st.n_post == 6
+    np.testing.assert_allclose(st.batch, want, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(st.batch.sum(axis=0), st.sum, rtol=1e-13, atol=1e-13)
+
+
 def test_out_of_box_proposals_are_rejected():
     P = W.make_hh_problem(16, 0.02, 101, require_spike=False)
     spec = P.model.with_(x_lo=(-100.0, 0.0, 0.0, 0.0), x_hi=(200.0, 1e-9, 1.0, 1.0))

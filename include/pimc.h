@@ -100,7 +100,12 @@ typedef struct {
  *   ptrace      [n_sweeps][7] FP64: p after every sweep of the call (written)
  *   acc         [PIMC_NACC] int64 acceptance counters (+=)
  *   stride      moments are accumulated at sweeps k >= burn with (k - burn) % stride == 0
- *               (the N_skip of Section 4.1; values <= 1 mean every sweep) */
+ *               (the N_skip of Section 4.1; values <= 1 mean every sweep)
+ *   batch       [nbatch][M+1][4] FP64 (nullable; requires sum): sum (x - xref) (+=) per run
+ *               of consecutive samples: of the ns samples one call takes, the i-th
+ *               (i = 0 .. ns-1) belongs to batch floor(i nbatch / ns), so batch b holds
+ *               ceil((b+1) ns / nbatch) - ceil(b ns / nbatch) samples (batch means for
+ *               the Monte Carlo error of the path means); nbatch >= 1 when batch is set */
 typedef struct {
   double* sum;
   double* sumsq;
@@ -109,6 +114,8 @@ typedef struct {
   int64_t* acc;
   int64_t burn;
   int64_t stride;
+  double* batch;
+  int64_t nbatch;
 } pimc_stats;
 
 /* What the LAST sweep of a call proposed and decided (every pointer nullable).
@@ -142,8 +149,8 @@ typedef struct {
 
 /* Per-window statistics of a batch (every pointer nullable; device memory).
  *   sum, sumsq [S][4] FP64 packed like X; xref [S][4] path precision;
- *   ptrace [B][n_sweeps][7] FP64; acc [B][PIMC_NACC] int64; burn, stride as
- *   for pimc_stats. */
+ *   ptrace [B][n_sweeps][7] FP64; acc [B][PIMC_NACC] int64; batch
+ *   [nbatch][S][4] FP64 packed like X; burn, stride, nbatch as for pimc_stats. */
 typedef struct {
   double* sum;
   double* sumsq;
@@ -152,6 +159,8 @@ typedef struct {
   int64_t* acc;
   int64_t burn;
   int64_t stride;
+  double* batch;
+  int64_t nbatch;
 } pimc_batch_stats;
 
 /* Create a context bound to HIP device `device` (it owns only its workspace:

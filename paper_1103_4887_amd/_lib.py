@@ -46,7 +46,8 @@ class Rng(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("xref", C.c_void_p),
-                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64)]
+                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64),
+                ("batch", C.c_void_p), ("nbatch", C.c_int64)]
 
 
 class Debug(C.Structure):
@@ -62,7 +63,8 @@ class Batch(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("xref", C.c_void_p),
-                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64)]
+                ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64),
+                ("batch", C.c_void_p), ("nbatch", C.c_int64)]
 
 
 class HmcStats(C.Structure):

@@ -132,16 +132,19 @@ class SweepStats:
     acc: Optional[torch.Tensor] = None
     burn: int = 0
     stride: int = 1
+    batch: Optional[torch.Tensor] = None    # [nbatch][sites][4] per-batch sums
 
     @staticmethod
     def allocate(win: Window, n_sweeps: int, burn: int = 0, moments: bool = True, trace: bool = True,
-                 stride: int = 1):
+                 stride: int = 1, nbatch: int = 0):
         dev = win.X.device
         st = SweepStats(burn=burn, stride=stride)
         if moments:
             st.sum = torch.zeros((win.M + 1, 4), dtype=torch.float64, device=dev)
             st.sumsq = torch.zeros_like(st.sum)
             st.xref = win.X.clone()
+            if nbatch > 0:
+                st.batch = torch.zeros((nbatch, win.M + 1, 4), dtype=torch.float64, device=dev)
         if trace:
             st.ptrace = torch.zeros((n_sweeps, 7), dtype=torch.float64, device=dev)
         st.acc = torch.zeros(L.PIMC_NACC, dtype=torch.int64, device=dev)
@@ -153,6 +156,8 @@ class SweepStats:
         s.ptrace, s.acc = _ptr(self.ptrace), _ptr(self.acc)
         s.burn = int(self.burn)
         s.stride = int(self.stride)
+        s.batch = _ptr(self.batch)
+        s.nbatch = int(self.batch.shape[0]) if self.batch is not None else 0
         return s
 
 
@@ -288,6 +293,8 @@ def pimc_run_batch(ctx: Context, spec, batch: PackedBatch, *, seed: int, sweep0:
         bs.sum, bs.sumsq, bs.xref = _ptr(stats.sum), _ptr(stats.sumsq), _ptr(stats.xref)
         bs.ptrace, bs.acc, bs.burn = _ptr(stats.ptrace), _ptr(stats.acc), int(stats.burn)
         bs.stride = int(stats.stride)
+        bs.batch = _ptr(stats.batch)
+        bs.nbatch = int(stats.batch.shape[0]) if stats.batch is not None else 0
         st = C.byref(bs)
     L.check(ctx.lib.pimc_run_batch(ctx.h, C.byref(m), C.byref(b), int(seed), int(sweep0), _ptr(w),
                                    int(n_sweeps), int(flags), st, _stream(stream)), "pimc_run_batch")

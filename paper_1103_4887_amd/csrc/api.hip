@@ -235,6 +235,21 @@ int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles,
   return 0;
 }
 
+// Per-batch sums: the statistics samples one call takes (sweeps k0 .. k0+n-1
+// with k >= burn and (k - burn) % stride == 0), their count and the sweep of
+// the first; bslice elements per batch slice.
+void fill_batch(pimc::SweepArgs& a, double* batch, int64_t nbatch, int64_t k0, int64_t n, int64_t bslice) {
+  if (!batch) return;
+  int64_t f = std::max(k0, a.burn);
+  const int64_t r = (f - a.burn) % a.stride;
+  if (r) f += a.stride - r;
+  a.batch = batch;
+  a.nbatch = nbatch;
+  a.kfirst = f;
+  a.nsamp = f < k0 + n ? (k0 + n - 1 - f) / a.stride + 1 : 0;
+  a.bslice = bslice;
+}
+
 void fill_consts(pimc::SweepArgs& a) {
   a.cf.init(a.m);
   a.cd.init(a.m);
@@ -392,6 +407,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
   if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
   if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
+  if (stats && stats->batch && (!stats->sum || stats->nbatch < 1)) return PIMC_ERR_ARG;
   if (n_sweeps == 0) return PIMC_OK;
   pimc::SweepArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -431,6 +447,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.acc = stats->acc;
     a.burn = stats->burn;
     a.stride = stats->stride > 1 ? stats->stride : 1;
+    fill_batch(a, stats->batch, stats->nbatch, (int64_t)rng.sweep0, n_sweeps, (path->M + 1) * 4);
   }
   fill_debug(a, debug);
   a.err = ctx->err;
@@ -502,6 +519,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   if (b->B < 1 || (b->prec != PIMC_FP64 && b->prec != PIMC_FP32)) return PIMC_ERR_ARG;
   if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
   if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
+  if (stats && stats->batch && (!stats->sum || stats->nbatch < 1)) return PIMC_ERR_ARG;
   if (n_sweeps == 0) return PIMC_OK;
   const int B = b->B;
   if (b->offsets[0] != 0) return PIMC_ERR_ARG;
@@ -585,6 +603,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     a.acc = stats->acc;
     a.burn = stats->burn;
     a.stride = stats->stride > 1 ? stats->stride : 1;
+    fill_batch(a, stats->batch, stats->nbatch, (int64_t)sweep0, n_sweeps, b->offsets[B] * 4);
   }
   a.err = ctx->err;
   if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s);

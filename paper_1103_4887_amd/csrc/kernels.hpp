@@ -36,6 +36,11 @@ struct SweepArgs {
   int64_t burn;
   int64_t stride;     // statistics every stride-th sweep from burn on
   int32_t stage;      // sites per LDS staging chunk of the statistics pass
+  double* batch;      // [nbatch][bslice] per-batch sums (nullable)
+  int64_t nbatch;
+  int64_t nsamp;      // statistics samples this call takes
+  int64_t kfirst;     // sweep of the first of them
+  int64_t bslice;     // elements of one batch slice (4 x sites)
   // last-sweep debug record (nullable)
   void* dbg_xprop;
   double* dbg_dA;

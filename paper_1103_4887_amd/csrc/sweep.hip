@@ -946,6 +946,13 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
       const T* xr = (const T*)a.xref + base * 4;
       double* su = a.sum + base * 4;
       double* sq = a.sumsq ? a.sumsq + base * 4 : nullptr;
+      // batch of this sample: the i-th of the call's nsamp samples belongs
+      // to batch floor(i nbatch / nsamp)
+      double* bt = nullptr;
+      if (a.batch) {
+        const int64_t si = ((int64_t)k - a.kfirst) / a.stride;
+        bt = a.batch + (si * a.nbatch / a.nsamp) * a.bslice + base * 4;
+      }
       const int Sst = a.stage;
       const int hi_site = last_tile ? M : tile0 + S - 1;   // this tile's sites only
       for (int c0 = tile0; c0 <= hi_site; c0 += Sst) {
@@ -968,7 +975,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         // eight independent elements per round: all loads are in flight
         // before the first add, so the loop is bandwidth- not latency-bound
         for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
-          double dv[8], s1[8], s2[8];
+          double dv[8], s1[8], s2[8], s3[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * NT;
@@ -976,6 +983,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
             s1[u] = e < cnt ? su[g] : 0.0;
             s2[u] = (e < cnt && sq) ? sq[g] : 0.0;
+            s3[u] = (e < cnt && bt) ? bt[g] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -984,6 +992,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             if (e < cnt) {
               su[g] = s1[u] + dv[u];
               if (sq) sq[g] = s2[u] + dv[u] * dv[u];
+              if (bt) bt[g] = s3[u] + dv[u];
             }
           }
         }

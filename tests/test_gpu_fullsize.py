@@ -39,12 +39,12 @@ def test_fp64_m256_full_chain_lockstep(ctx):
     prob = W.config_problem("c1", init="truth", require_spike=False)
     n, burn = c["sweeps"], c["burn"]
     X, p = prob.X0.copy(), prob.p0.copy()
-    st = OS.Stats(prob.M, 4, 7, n, burn=burn, xref=prob.X0.copy())
+    st = OS.Stats(prob.M, 4, 7, n, burn=burn, xref=prob.X0.copy(), nbatch=32)
     print("oracle c1 chain", flush=True)
     OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=1, sweep0=0, n_sweeps=n,
            w_state=prob.w_state, w_param=prob.w_param, stats=st)
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
-    gst = P.SweepStats.allocate(win, n, burn=burn)
+    gst = P.SweepStats.allocate(win, n, burn=burn, nbatch=32)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     print("gpu c1 chain", flush=True)
     P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=1, sweep0=0, w=w, n_sweeps=n, stats=gst)
@@ -56,6 +56,8 @@ def test_fp64_m256_full_chain_lockstep(ctx):
     # posterior means and variances of the states (sums over the second half)
     np.testing.assert_allclose(gst.sum.cpu().numpy(), st.sum, rtol=1e-8, atol=1e-8)
     np.testing.assert_allclose(gst.sumsq.cpu().numpy(), st.sumsq, rtol=1e-8, atol=1e-10)
+    # batch means (32 runs of consecutive samples) for the MCSE of the path means
+    np.testing.assert_allclose(gst.batch.cpu().numpy(), st.batch, rtol=1e-8, atol=1e-8)
 
 
 def test_c4_batch_sampled_windows_equal_single_runs(ctx):

@@ -233,11 +233,12 @@ def test_multi_sweep_fp64_chain_and_stats(ctx):
     prob = _problem(300, init="guess", mask=W.configs.MASK_C1)
     n = 40
     X, p = prob.X0.copy(), prob.p0.copy()
-    st = OS.Stats(prob.M, 4, 7, n, burn=110, xref=prob.X0.copy(), stride=4)
+    # samples after sweeps 110, 114, .., 138 (eight), in batches of 3, 3, 2
+    st = OS.Stats(prob.M, 4, 7, n, burn=110, xref=prob.X0.copy(), stride=4, nbatch=3)
     OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=3, sweep0=100, n_sweeps=n,
            w_state=prob.w_state, w_param=prob.w_param, stats=st)
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
-    gst = P.SweepStats.allocate(win, n, burn=110, stride=4)
+    gst = P.SweepStats.allocate(win, n, burn=110, stride=4, nbatch=3)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=3, sweep0=100, w=w, n_sweeps=n, stats=gst)
     assert ctx.sync() == 0
@@ -246,6 +247,7 @@ def test_multi_sweep_fp64_chain_and_stats(ctx):
     np.testing.assert_allclose(gst.ptrace.cpu().numpy(), st.ptrace, rtol=1e-12)
     np.testing.assert_allclose(gst.sum.cpu().numpy(), st.sum, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(gst.sumsq.cpu().numpy(), st.sumsq, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gst.batch.cpu().numpy(), st.batch, rtol=1e-9, atol=1e-9)
     np.testing.assert_array_equal(gst.acc.cpu().numpy(), st.acc)
 
 
@@ -356,7 +358,8 @@ def test_tiled_batch_equals_single_runs(ctx, Ms, T):
     bst = P.SweepStats(sum=torch.zeros(batch.X.shape, dtype=torch.float64, device=dev),
                        sumsq=torch.zeros(batch.X.shape, dtype=torch.float64, device=dev), xref=batch.X.clone(),
                        ptrace=torch.zeros((len(Ms), n, 7), dtype=torch.float64, device=dev),
-                       acc=torch.zeros((len(Ms), 10), dtype=torch.int64, device=dev), burn=0)
+                       acc=torch.zeros((len(Ms), 10), dtype=torch.int64, device=dev), burn=0,
+                       batch=torch.zeros((5,) + tuple(batch.X.shape), dtype=torch.float64, device=dev))
     ctx.set_tiles(T)
     try:
         print(f"tiled batch Ms={Ms} T={T}", flush=True)
@@ -365,7 +368,7 @@ def test_tiled_batch_equals_single_runs(ctx, Ms, T):
         for i, q in enumerate(probs):
             ctx.set_tiles(1)
             win = P.Window.from_arrays(q.X0, q.p0, q.y, q.I, "fp32")
-            st = P.SweepStats.allocate(win, n, burn=0)
+            st = P.SweepStats.allocate(win, n, burn=0, nbatch=5)
             P.pimc_sweep(ctx, spec, win, seed=8, chain=chains[i], sweep0=3, w=w, n_sweeps=n, stats=st)
             assert ctx.sync() == 0
             a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
@@ -374,6 +377,8 @@ def test_tiled_batch_equals_single_runs(ctx, Ms, T):
             np.testing.assert_array_equal(bst.acc[i].cpu().numpy(), st.acc.cpu().numpy())
             np.testing.assert_allclose(bst.ptrace[i].cpu().numpy(), st.ptrace.cpu().numpy(), rtol=1e-14)
             np.testing.assert_allclose(bst.sum[a:b].cpu().numpy(), st.sum.cpu().numpy(), rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(bst.batch[:, a:b].cpu().numpy(), st.batch.cpu().numpy(), rtol=1e-12,
+                                       atol=1e-12)
     finally:
         ctx.set_tiles(0)
 

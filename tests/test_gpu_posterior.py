@@ -93,7 +93,7 @@ def test_fp32_chains_match_oracle_posterior_means():
     print("parameter z:", np.round(zp, 2), flush=True)
     big = np.flatnonzero(np.abs(zx) > 3.0)
     print(f"state z: max |z| {np.abs(zx).max():.2f}, beyond 3: {len(big)} of {zx.size}",
-          [(int(i) // 4, "VmhN"[int(i) % 4], round(float(zx[i]), 2)) for i in big], flush=True)
+          [(int(i) // 4, "Vmhn"[int(i) % 4], round(float(zx[i]), 2)) for i in big], flush=True)
     assert np.all(np.abs(zp) <= 3.0), zp
     assert (np.abs(zx) > 3.0).sum() <= 0.01 * zx.size
     assert np.all(np.abs(zx) <= 5.0)

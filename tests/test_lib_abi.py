@@ -49,7 +49,7 @@ def test_struct_layout_matches_header():
     assert C.sizeof(L.Model) == 8 * (1 + 1 + 4 + 1 + 12 + 8 + 14) + 8
     assert C.sizeof(L.Path) == 8 + 8 + 4 * 8
     assert C.sizeof(L.Rng) == 24
-    assert C.sizeof(L.Stats) == 7 * 8
-    assert C.sizeof(L.BatchStats) == 7 * 8
+    assert C.sizeof(L.Stats) == 9 * 8
+    assert C.sizeof(L.BatchStats) == 9 * 8
     assert C.sizeof(L.Debug) == 6 * 8
     assert C.sizeof(L.Batch) == 8 + 6 * 8

@@ -128,26 +128,18 @@ __device__ __forceinline__ void dFVdp_T(const Consts<T>& C, T V, T m, T h, T n, 
 }
 
 
-// Parameter state of chain `ch` at leapfrog kernel s (identical in every
-// block of the chain): p(s), and the momentum rp(s-1/2) that moved it there.
-__device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, bool last_step, double (&ps)[7],
-                                             double (&rps)[7], double (&gp_prev)[7], double* red) {
-  (void)last_step;
-  const int b0 = a.bfirst[ch], b1 = a.bfirst[ch + 1];
-  const double* part = a.part + (int64_t)((s - 1) & 1) * a.nblocks * 16;
-  // fixed-order reduction of the previous kernel's partials of this chain
-  chain_sum<7>(part, b0, b1, 0, red + 16, red, (int)threadIdx.x);
-#pragma unroll
-  for (int l = 0; l < 7; ++l) gp_prev[l] = red[l];
-  const double c = s == 1 ? 0.5 : 1.0;
-  const double* rp_in = a.rpbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
-  const double* p_in = s == 1 ? a.p + (int64_t)ch * 7 : a.pbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
+// Parameter part of a leapfrog step for one chain: the momentum
+// rp(s-1/2) = rp_in - c e gp (c = 1/2 on the first step), then the drift
+// p(s) = p_in + e minv rp(s-1/2), reflected once at the box walls with the
+// momentum negated.
+__device__ __forceinline__ void param_drift(const HmcArgs& a, double c, const double (&gp)[7],
+                                            const double (&rp_in)[7], const double (&p_in)[7], double (&ps)[7],
+                                            double (&rps)[7]) {
 #pragma unroll
   for (int l = 0; l < 7; ++l) {
     const bool on = (a.m.p_mask >> l) & 1;
-    rps[l] = on ? rp_in[l] - c * a.eps * gp_prev[l] : 0.0;
+    rps[l] = on ? rp_in[l] - c * a.eps * gp[l] : 0.0;
     double q = on ? p_in[l] + a.eps * a.minv[4 + l] * rps[l] : p_in[l];
-    // one reflection at the box walls, momentum negated
     if (on && q < a.m.p_lo[l]) {
       q = 2.0 * a.m.p_lo[l] - q;
       rps[l] = -rps[l];
@@ -157,6 +149,94 @@ __device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, bo
     }
     ps[l] = q;
   }
+}
+
+// Parameter state of chain `ch` at leapfrog kernel s (identical in every
+// block of the chain): p(s), and the momentum rp(s-1/2) that moved it there.
+__device__ __forceinline__ void chain_params(const HmcArgs& a, int ch, int s, double (&ps)[7], double (&rps)[7],
+                                             double* red) {
+  const int b0 = a.bfirst[ch], b1 = a.bfirst[ch + 1];
+  const double* part = a.part + (int64_t)((s - 1) & 1) * a.nblocks * 16;
+  // fixed-order reduction of the previous kernel's partials of this chain
+  chain_sum<7>(part, b0, b1, 0, red + 16, red, (int)threadIdx.x);
+  double gp[7], rp_in[7], p_in[7];
+  const double* rpi = a.rpbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
+  const double* pi = s == 1 ? a.p + (int64_t)ch * 7 : a.pbuf + (int64_t)((s - 1) & 1) * a.B * 7 + (int64_t)ch * 7;
+#pragma unroll
+  for (int l = 0; l < 7; ++l) {
+    gp[l] = red[l];
+    rp_in[l] = rpi[l];
+    p_in[l] = pi[l];
+  }
+  param_drift(a, s == 1 ? 0.5 : 1.0, gp, rp_in, p_in, ps, rps);
+}
+
+// One drift of a site, q + e minv r, reflected once at the walls of the
+// state box; bit c of the result marks a reflected component (its momentum
+// is negated at the kick).
+template <typename T>
+__device__ __forceinline__ uint32_t drift_site(const Consts<T>& C, const T (&minv)[4], T e, T (&q)[4],
+                                               const T (&r)[4]) {
+  uint32_t flip = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    q[c] = q[c] + e * minv[c] * r[c];
+    if (q[c] < C.lo[c]) {
+      q[c] = (T)2 * C.lo[c] - q[c];
+      flip |= 1u << c;
+    } else if (q[c] > C.hi[c]) {
+      q[c] = (T)2 * C.hi[c] - q[c];
+      flip |= 1u << c;
+    }
+  }
+  return flip;
+}
+
+// dA/dx at site n (LDS index j) from the stencil of positions lq and fields
+// lF with the site's Jacobian J; vl0 = beta Rd_V eps_V of link n (0 at n = 0).
+template <typename T>
+__device__ __forceinline__ void site_grad(const HmcArgs& a, const Consts<T>& C, const HmcJ<T>& J,
+                                          const T (*lq)[4], const T (*lF)[4], int j, int n, int M, T y_own,
+                                          const T (&x)[4], T (&g)[4], T& vl0) {
+  const T h = C.h;
+  const T beta = (T)a.m.beta;
+  T vl[4] = {0, 0, 0, 0}, vr[4] = {0, 0, 0, 0};
+  if (n >= 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T el = (x[c] - lq[j - 1][c]) - h * (lF[j][c] + lF[j - 1][c]);
+      vl[c] = beta * (T)a.m.Rd[c] * el;
+    }
+  }
+  if (n + 1 <= M) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      vr[c] = beta * (T)a.m.Rd[c] * ((lq[j + 1][c] - x[c]) - h * (lF[j + 1][c] + lF[j][c]));
+  }
+  T u[4], w[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    u[c] = vl[c] - vr[c];
+    w[c] = vl[c] + vr[c];
+  }
+  g[0] = u[0] - h * (J.VV * w[0] + J.gV[0] * w[1] + J.gV[1] * w[2] + J.gV[2] * w[3]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) g[1 + q] = u[1 + q] - h * (J.Vg[q] * w[0] + J.gg[q] * w[1 + q]);
+  if (n >= 1) g[0] -= (T)a.m.Ro * (y_own - x[0]);
+  vl0 = vl[0];
+}
+
+// dA/dp of link n >= 1 (sites j - 1, j of the LDS stencil): per-site terms in
+// the site precision, written as FP64 partials part[0..6].
+template <typename T, int N>
+__device__ __forceinline__ void link_dadp(const HmcArgs& a, const Consts<T>& C, const T (*lq)[4], const T* lI,
+                                          int j, const T (&x)[4], T vl0, double (&part)[N]) {
+  T d1[7], d0[7];
+  dFVdp_T(C, x[0], x[1], x[2], x[3], lI[j], d1);
+  dFVdp_T(C, lq[j - 1][0], lq[j - 1][1], lq[j - 1][2], lq[j - 1][3], lI[j - 1], d0);
+  const T f = (T)(-0.5 * a.m.dt) * vl0;
+#pragma unroll
+  for (int l = 0; l < 7; ++l) part[l] = (double)(f * (d1[l] + d0[l]));
 }
 
 }  // namespace
@@ -205,21 +285,15 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         T q[4];
         uint32_t flip = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          q[c] = Qin[(int64_t)n * 4 + c];
-          if (MODE != 0) {
-            q[c] = q[c] + e * minv_s[c] * Rin[(int64_t)n * 4 + c];
-            // one reflection at the box walls (the momentum is negated below)
-            if (q[c] < C.lo[c]) {
-              q[c] = (T)2 * C.lo[c] - q[c];
-              flip |= 1u << c;
-            } else if (q[c] > C.hi[c]) {
-              q[c] = (T)2 * C.hi[c] - q[c];
-              flip |= 1u << c;
-            }
-          }
-          lq[j][c] = q[c];
+        for (int c = 0; c < 4; ++c) q[c] = Qin[(int64_t)n * 4 + c];
+        if (MODE != 0) {
+          T rr[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rr[c] = Rin[(int64_t)n * 4 + c];
+          flip = drift_site(C, minv_s, e, q, rr);
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lq[j][c] = q[c];
         lflip[j] = (uint8_t)flip;
         lI[j] = Ip[n];
       }
@@ -238,12 +312,12 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
   }
 
   // ---- parameters at this step -------------------------------------------
-  double ps[7], rps[7], gpp[7];
+  double ps[7], rps[7];
   if (MODE == 0) {
 #pragma unroll
     for (int l = 0; l < 7; ++l) ps[l] = a.p[(int64_t)ch * 7 + l];
   } else {
-    chain_params(a, ch, s, MODE == 2, ps, rps, gpp, red);
+    chain_params(a, ch, s, ps, rps, red);
     bool out = false;
 #pragma unroll
     for (int l = 0; l < 7; ++l)
@@ -315,31 +389,8 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       for (int c = 0; c < 4; ++c) out = out || !(x[c] >= C.lo[c] && x[c] <= C.hi[c]);
       if (out) atomicOr(&a.outside[ch], 1u);
     }
-    const T h = C.h;
-    const T beta = (T)a.m.beta;
-    T vl[4] = {0, 0, 0, 0}, vr[4] = {0, 0, 0, 0}, el[4] = {0, 0, 0, 0};
-    if (n >= 1) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        el[c] = (x[c] - lq[j - 1][c]) - h * (lF[j][c] + lF[j - 1][c]);
-        vl[c] = beta * (T)a.m.Rd[c] * el[c];
-      }
-    }
-    if (n + 1 <= M) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        vr[c] = beta * (T)a.m.Rd[c] * ((lq[j + 1][c] - x[c]) - h * (lF[j + 1][c] + lF[j][c]));
-    }
-    T u[4], w[4], g[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      u[c] = vl[c] - vr[c];
-      w[c] = vl[c] + vr[c];
-    }
-    g[0] = u[0] - h * (J.VV * w[0] + J.gV[0] * w[1] + J.gV[1] * w[2] + J.gV[2] * w[3]);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) g[1 + q] = u[1 + q] - h * (J.Vg[q] * w[0] + J.gg[q] * w[1 + q]);
-    if (n >= 1) g[0] -= (T)a.m.Ro * (y_own - x[0]);
+    T g[4], vl0;
+    site_grad(a, C, J, lq, lF, j, n, M, y_own, x, g, vl0);
 
     // momenta: drawn (MODE 0) or r(s-1/2); kick; kinetic energy partial
     T r[4];
@@ -409,13 +460,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         }
         part[8] = 0.5 * s2;
       }
-      // dA/dp of link n: per-site terms in the site precision, summed in FP64
-      T d1[7], d0[7];
-      dFVdp_T(C, x[0], x[1], x[2], x[3], lI[j], d1);
-      dFVdp_T(C, lq[j - 1][0], lq[j - 1][1], lq[j - 1][2], lq[j - 1][3], lI[j - 1], d0);
-      const T f = (T)(-0.5 * a.m.dt) * vl[0];
-#pragma unroll
-      for (int l = 0; l < 7; ++l) part[l] = (double)(f * (d1[l] + d0[l]));
+      link_dadp(a, C, lq, lI, j, x, vl0, part);
     }
   }
   // ---- block partials (interior steps carry only dA/dp) --------------------

@@ -43,9 +43,11 @@ TRAFFIC = {"sweep_hip_sha256": "087e6b28ebad95dfefc803e69adb92b6604dbf7c029614d0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="sweeps (proposals for c5); default 100000 for one window, 2000 for c4, 300 for c5")
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c2",
+                    help="c1-c3: one window; c4: the uneven batch; c5: HMC on 64 chains (default c2)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="sites per thread (0: autotune)")
@@ -232,6 +234,153 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
     }
 
 
+def _timed(stream, fn):
+    """Run fn between two HIP events on `stream`; returns (seconds on the
+    device clock, wall seconds, fn's result)."""
+    import torch
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    r = fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall, r
+
+
+def _common(metric, value, unit, K, Wm, gpu_s, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": K, "warmup": Wm,
+            "ms_per_step": gpu_s * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def bench_batch(args, ctx):
+    """The batched workload: 512 HH windows of uneven M (each with its own
+    drive, noise and true parameters) swept together by one launch per call
+    (the captured batch graph).  One step = one sweep of every window."""
+    import numpy as np
+    import torch
+
+    import paper_1103_4887_amd as P
+    from paper_1103_4887_amd import autotune
+    import workloads as W
+
+    cfg = W.CONFIGS[args.config]
+    probs = W.config_batch(args.config, workers=max(1, min(16, os.cpu_count() or 1)))
+    spec = probs[0].model
+    B = len(probs)
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], list(range(B)), "fp32")
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+    shape = autotune.tune_batch(ctx, spec, batch, w)
+    K = args.steps or 2000
+    Wm = args.warmup
+    P.pimc_run_batch(ctx, spec, batch, seed=cfg["data_seed"], sweep0=0, w=w, n_sweeps=max(Wm, 1))
+    assert ctx.sync() == 0
+    st = P.SweepStats(acc=torch.zeros((B, P._lib.PIMC_NACC), dtype=torch.int64, device=batch.X.device))
+    stream = torch.cuda.current_stream()
+    gpu_s, wall, _ = _timed(stream, lambda: P.pimc_run_batch(ctx, spec, batch, seed=cfg["data_seed"],
+                                                              sweep0=max(Wm, 1), w=w, n_sweeps=K, stats=st))
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported an error")
+    sites = int(batch.offsets[-1])
+    rate = sites * K / gpu_s
+    acc = st.acc.cpu().numpy()
+    achieved = SLOTS_PER_SITE_UPDATE * rate
+    out = _common("path site-updates/s, uneven batch of HH windows, 1 GPU", rate, "site-updates/s", K, Wm,
+                  gpu_s, "f32",
+                  {"workload": f"{args.config}: {B} HH windows, M uniform in [{cfg['M_lo']}, {cfg['M_hi']}] "
+                               f"({sites} sites), dt={spec.dt} ms, fp32 sites + f64 reductions, params mask "
+                               f"0x{spec.p_mask:x}, one launch per call, {K} sweeps",
+                   "windows": B, "sites": sites, "launch": {"K": shape[0], "tiles": shape[1]}})
+    out["accept_rate"] = {"sites": float(acc[:, :2].sum() / (sites * K))}
+    out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
+                       "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
+                       "kernel": "sweep_kernel", "slots_per_site_update": SLOTS_PER_SITE_UPDATE,
+                       "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3}
+    if not args.no_cpu_baseline:
+        med = probs[int(np.argsort([q.M for q in probs])[B // 2])]
+        out["cpu_baseline"] = cpu_baseline(med, args.cpu_seconds)
+        out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]
+    return out
+
+
+def bench_hmc(args, ctx):
+    """HMC on the 64-chain workload: pilot masses and dual-averaged step size
+    (untimed), then K proposals of L leapfrog steps replayed from one
+    captured graph.  One step = one proposal of every chain."""
+    import numpy as np
+    import torch
+
+    import paper_1103_4887_amd as P
+    from paper_1103_4887_amd import autotune
+    from paper_1103_4887_amd import hmc as H
+    import workloads as W
+
+    cfg = W.CONFIGS[args.config]
+    prob = W.config_problem(args.config, init="truth")
+    spec = prob.model
+    B, L = cfg["chains"], cfg["leapfrog"]
+    batch = P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    autotune.tune_batch(ctx, spec, batch, w)
+    minv = H.pilot_minv(ctx, spec, batch, w, seed=prob.seed + 1, sweeps=2000)
+    tun = H.tune_eps(ctx, spec, batch, minv, seed=prob.seed + 2, L_steps=L, warmup=200, eps0=0.01)
+    K = args.steps or 300
+    Wm = min(args.warmup, 50)
+    H.sample(ctx, spec, batch, tun, seed=prob.seed + 2, L_steps=L, n=max(Wm, 1), k0=200)
+    stream = torch.cuda.current_stream()
+    gpu_s, wall, sh = _timed(stream, lambda: H.sample(ctx, spec, batch, tun, seed=prob.seed + 2, L_steps=L, n=K,
+                                                      k0=200 + max(Wm, 1)))
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported an error")
+    sites = B * (prob.M + 1)
+    rate = sites * L * K / gpu_s
+    mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
+    ess, _, _ = _post_stats(sh.ptrace.cpu().numpy()[:, K // 2:], mask)
+    acc = sh.acc.cpu().numpy()
+    out = _common("site-leapfrogs/s + param ESS/s, HMC, HH M=16384 x 64 chains, 1 GPU", rate, "site-leapfrogs/s",
+                  K, Wm, gpu_s, "f32",
+                  {"workload": f"{args.config}: HMC on {B} chains of the HH window M={prob.M}, dt={spec.dt} ms, "
+                               f"{L} leapfrog steps per proposal, fp32 sites + f64 Hamiltonian, params mask "
+                               f"0x{spec.p_mask:x}, {K} proposals",
+                   "chains": B, "M": prob.M, "leapfrog_steps": L, "eps": tun.eps})
+    out["param_ess_per_s"] = float(ess.min() / gpu_s)
+    out["param_ess"] = [float(v) for v in ess]
+    out["accept_rate"] = float(acc[:, 0].sum() / (B * K))
+    # per site-leapfrog the kernels move q, r (read and write) and read y, I
+    out["roofline"] = {"bound": "hbm", "achieved": 72.0 * rate / 1e9, "peak": 8000.0, "unit": "GB/s",
+                       "frac": 72.0 * rate / 8e12, "traffic": None, "kernel": "hmc_step_kernel",
+                       "bytes_per_site_leapfrog": 72, "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_hmc(prob, tun, L, args.cpu_seconds)
+        out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]
+    return out
+
+
+def cpu_baseline_hmc(prob, tun, L, budget_s: float):
+    """The oracle's HMC proposal, untouched, on one chain for a bounded number of proposals."""
+    from oracle import hmc as OH
+
+    X = prob.X0.copy()
+    p = prob.p0.copy()
+    n = 0
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+    while time.perf_counter() - t0 < budget_s:
+        X, p, _, _ = OH.hmc_proposal(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=0, k=n, e=tun.eps,
+                                     L=L, minv_state=tun.minv[:4], minv_param=tun.minv[4:])
+        n += 1
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {"value": (prob.M + 1) * L * n / wall, "unit": "site-leapfrogs/s",
+            "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "sample": f"{n} proposals of one M={prob.M} chain ({wall:.1f} s)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -246,6 +395,12 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config in ("c4", "c5"):
+        ctx = P.Context(0)
+        out = (bench_batch if args.config == "c4" else bench_hmc)(args, ctx)
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     cfg = W.CONFIGS[args.config]
     prob = W.config_problem(args.config)
     prec = cfg["prec"]
@@ -253,7 +408,7 @@ def main():
     spec = prob.model
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, prec)
     w = P.widths_tensor(prob.w_state, prob.w_param)
-    K, Wm = args.steps, args.warmup
+    K, Wm = args.steps or 100000, args.warmup
     stream = torch.cuda.current_stream()
     if args.tiles < 0 and not args.tile:
         shape = autotune.tune(ctx, spec, win, w)

@@ -975,7 +975,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
         // eight independent elements per round: all loads are in flight
         // before the first add, so the loop is bandwidth- not latency-bound
         for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
-          double dv[8], s1[8], s2[8], s3[8];
+          double dv[8], s1[8], s2[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * NT;
@@ -983,7 +983,6 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
             s1[u] = e < cnt ? su[g] : 0.0;
             s2[u] = (e < cnt && sq) ? sq[g] : 0.0;
-            s3[u] = (e < cnt && bt) ? bt[g] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -992,7 +991,25 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
             if (e < cnt) {
               su[g] = s1[u] + dv[u];
               if (sq) sq[g] = s2[u] + dv[u] * dv[u];
-              if (bt) bt[g] = s3[u] + dv[u];
+            }
+          }
+        }
+        // the batch sums in a pass of their own, so that runs without them
+        // keep the registers of the pass above
+        if (bt) {
+          for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
+            double dv[8], s3[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int e = e0 + u * NT;
+              const int64_t g = (int64_t)c0 * 4 + e;
+              dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
+              s3[u] = e < cnt ? bt[g] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int e = e0 + u * NT;
+              if (e < cnt) bt[(int64_t)c0 * 4 + e] = s3[u] + dv[u];
             }
           }
         }

@@ -716,7 +716,7 @@ extern "C" int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch
       if ((r = pimc::launch_hmc_proposal(a, fp64, L, s))) return r;
     return PIMC_OK;
   }
-  // The L + 4 launches of one proposal take fixed arguments (the proposal
+  // The L + 3 launches of one proposal take fixed arguments (the proposal
   // index is in device memory), so they are captured once and replayed on
   // the caller's stream.  Capture happens on a private stream because the
   // caller's may be the legacy default stream, which cannot be captured;

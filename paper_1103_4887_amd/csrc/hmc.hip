@@ -251,6 +251,10 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
   __shared__ double red[16 + HB];   // [0..15] results, then chain_sum scratch
   __shared__ double lsum[HB / 16 * NPART];
   __shared__ uint8_t lflip[HB + 2];   // bit c: component c reflected in this drift
+  // FP64 fields for the Hamiltonian (first and last kernels, FP32 sites):
+  // each site's once, shared by its two links
+  constexpr bool F64 = MODE != 1 && sizeof(T) == 4;
+  __shared__ double lF64[F64 ? HB + 2 : 1][4];
   const int t = threadIdx.x;
   const int b = blockIdx.x;
   const int ch = a.bmap[b];
@@ -371,6 +375,22 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       for (int c = 0; c < 4; ++c) lF[j][c] = F[c];
     }
   }
+  if constexpr (F64) {
+    // own site and the left halo site (the links n - 1 -> n of the block)
+    Consts<double> CD = a.cd;
+    CD.set_p(ps);
+    for (int j = t + 1; j >= t; --j) {
+      const int n = site0 - 1 + j;
+      if ((j == t + 1 || t == 0) && n >= 0 && n <= M) {
+        double xd[4], Fd[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xd[c] = (double)lq[j][c];
+        hh_F(CD, xd, (double)lI[j], Fd);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lF64[j][c] = Fd[c];
+      }
+    }
+  }
   __syncthreads();
 
   // ---- own site: gradient, kick, partials ---------------------------------
@@ -443,19 +463,19 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         part[7] = 0.5 * a.m.Ro * d * d;
         double s2 = 0.0;
         // FP64 model error of link n for the Hamiltonian
-        double x1[4], x0[4], F1[4], F0[4];
-        Consts<double> CD = a.cd;
-        CD.set_p(ps);
+        const double hd = a.cd.h;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          x1[c] = (double)x[c];
-          x0[c] = (double)lq[j - 1][c];
-        }
-        hh_F(CD, x1, (double)lI[j], F1);
-        hh_F(CD, x0, (double)lI[j - 1], F0);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double ee = (x1[c] - x0[c]) - CD.h * (F1[c] + F0[c]);
+          const double x1 = (double)x[c], x0 = (double)lq[j - 1][c];
+          double F1, F0;
+          if constexpr (F64) {
+            F1 = lF64[j][c];
+            F0 = lF64[j - 1][c];
+          } else {   // FP64 sites: the fields of the step itself
+            F1 = (double)lF[j][c];
+            F0 = (double)lF[j - 1][c];
+          }
+          const double ee = (x1 - x0) - hd * (F1 + F0);
           s2 += a.m.Rd[c] * ee * ee;
         }
         part[8] = 0.5 * s2;
@@ -544,6 +564,8 @@ __global__ void hmc_restore_kernel(HmcArgs a, int L) {
   const int64_t base = a.offsets[ch];
   const int M = (int)(a.offsets[ch + 1] - base - 1);
   const int n = (b - a.bfirst[ch]) * HB + threadIdx.x;
+  // the next proposal's index (no kernel of this proposal reads it any more)
+  if (b == 0 && threadIdx.x == 0) *a.kptr += 1;
   if (n > M) return;
   const bool ok = a.accepted[ch] != 0;
   const T* src = (const T*)(ok ? ((L & 1) ? a.Q1 : a.X) : a.X0) + (base + n) * 4;
@@ -553,8 +575,6 @@ __global__ void hmc_restore_kernel(HmcArgs a, int L) {
     for (int c = 0; c < 4; ++c) X[c] = src[c];
   }
 }
-
-__global__ void hmc_advance_kernel(uint64_t* kptr) { *kptr += 1; }
 
 int launch_hmc_proposal(const HmcArgs& a, bool fp64, int L, hipStream_t s) {
   const dim3 gb(a.nblocks), tb(HB);
@@ -572,7 +592,6 @@ int launch_hmc_proposal(const HmcArgs& a, bool fp64, int L, hipStream_t s) {
     hipLaunchKernelGGL(hmc_restore_kernel<double>, gb, tb, 0, s, a, L);
   else
     hipLaunchKernelGGL(hmc_restore_kernel<float>, gb, tb, 0, s, a, L);
-  hipLaunchKernelGGL(hmc_advance_kernel, dim3(1), dim3(1), 0, s, a.kptr);
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }
 

@@ -193,11 +193,12 @@ __device__ __forceinline__ uint32_t drift_site(const Consts<T>& C, const T (&min
 }
 
 // dA/dx at site n (LDS index j) from the stencil of positions lq and fields
-// lF with the site's Jacobian J; vl0 = beta Rd_V eps_V of link n (0 at n = 0).
+// lF with the site's Jacobian J; w0 = beta Rd_V (eps_V of link n + eps_V of
+// link n + 1), the links that exist.
 template <typename T>
 __device__ __forceinline__ void site_grad(const HmcArgs& a, const Consts<T>& C, const HmcJ<T>& J,
                                           const T (*lq)[4], const T (*lF)[4], int j, int n, int M, T y_own,
-                                          const T (&x)[4], T (&g)[4], T& vl0) {
+                                          const T (&x)[4], T (&g)[4], T& w0) {
   const T h = C.h;
   const T beta = (T)a.m.beta;
   T vl[4] = {0, 0, 0, 0}, vr[4] = {0, 0, 0, 0};
@@ -223,20 +224,21 @@ __device__ __forceinline__ void site_grad(const HmcArgs& a, const Consts<T>& C, 
 #pragma unroll
   for (int q = 0; q < 3; ++q) g[1 + q] = u[1 + q] - h * (J.Vg[q] * w[0] + J.gg[q] * w[1 + q]);
   if (n >= 1) g[0] -= (T)a.m.Ro * (y_own - x[0]);
-  vl0 = vl[0];
+  w0 = w[0];
 }
 
-// dA/dp of link n >= 1 (sites j - 1, j of the LDS stencil): per-site terms in
+// dA/dp contribution of site n: dF_V/dp at the site enters the errors of
+// its two links, so the link sum of the action's derivative regroups into
+// -(dt/2) w0 dF_V/dp(x_n) per site (w0 from site_grad); per-site terms in
 // the site precision, written as FP64 partials part[0..6].
 template <typename T, int N>
-__device__ __forceinline__ void link_dadp(const HmcArgs& a, const Consts<T>& C, const T (*lq)[4], const T* lI,
-                                          int j, const T (&x)[4], T vl0, double (&part)[N]) {
-  T d1[7], d0[7];
-  dFVdp_T(C, x[0], x[1], x[2], x[3], lI[j], d1);
-  dFVdp_T(C, lq[j - 1][0], lq[j - 1][1], lq[j - 1][2], lq[j - 1][3], lI[j - 1], d0);
-  const T f = (T)(-0.5 * a.m.dt) * vl0;
+__device__ __forceinline__ void site_dadp(const HmcArgs& a, const Consts<T>& C, const T* lI, int j, const T (&x)[4],
+                                          T w0, double (&part)[N]) {
+  T d[7];
+  dFVdp_T(C, x[0], x[1], x[2], x[3], lI[j], d);
+  const T f = (T)(-0.5 * a.m.dt) * w0;
 #pragma unroll
-  for (int l = 0; l < 7; ++l) part[l] = (double)(f * (d1[l] + d0[l]));
+  for (int l = 0; l < 7; ++l) part[l] = (double)(f * d[l]);
 }
 
 }  // namespace
@@ -409,8 +411,8 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       for (int c = 0; c < 4; ++c) out = out || !(x[c] >= C.lo[c] && x[c] <= C.hi[c]);
       if (out) atomicOr(&a.outside[ch], 1u);
     }
-    T g[4], vl0;
-    site_grad(a, C, J, lq, lF, j, n, M, y_own, x, g, vl0);
+    T g[4], w0;
+    site_grad(a, C, J, lq, lF, j, n, M, y_own, x, g, w0);
 
     // momenta: drawn (MODE 0) or r(s-1/2); kick; kinetic energy partial
     T r[4];
@@ -456,7 +458,7 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       for (int c = 0; c < 4; ++c) kin += 0.5 * (double)rn[c] * (double)rn[c] * a.minv[c];
       part[9] = kin;
     }
-    // action terms (initial and last kernels) and dA/dp of link n
+    // action terms of link n (initial and last kernels), then dA/dp of site n
     if (n >= 1) {
       if (MODE != 1) {
         const double d = (double)y_own - (double)x[0];
@@ -480,8 +482,8 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         }
         part[8] = 0.5 * s2;
       }
-      link_dadp(a, C, lq, lI, j, x, vl0, part);
     }
+    site_dadp(a, C, lI, j, x, w0, part);
   }
   // ---- block partials (interior steps carry only dA/dp) --------------------
   double* pout = a.part + (int64_t)(s & 1) * a.nblocks * 16 + (int64_t)b * 16;

@@ -102,6 +102,8 @@ def _post_stats(traces, mask):
 
     ess = np.array([diag.ess_columns(t[:, mask]) for t in traces]).sum(axis=0)
     cm = traces[:, :, mask].mean(axis=1)
+    if len(cm) < 2:   # one chain: no spread of chain means to take
+        return ess, cm.mean(axis=0), np.full(cm.shape[1], np.nan)
     return ess, cm.mean(axis=0), cm.std(axis=0, ddof=1) / np.sqrt(len(cm))
 
 

@@ -19,6 +19,9 @@ struct pimc_ctx {
   size_t partial_cap = 0;         // in doubles
   int64_t* offsets = nullptr;     // batch offsets (device copy)
   int32_t* order = nullptr;       // batch launch order (device)
+  int8_t* blockK = nullptr;       // batch: sites per thread of each block (device)
+  int blockK_NT = 0;              // workgroup size blockK was computed for (0: none)
+  bool uniform_batch_K = false;   // every window of a batch with the launch's sites per thread
   size_t batch_cap = 0;           // in windows
   int tile_K = 0;                 // 0 = automatic choice of sites per thread
   int tiles = 0;                  // 0 = automatic number of time tiles per window
@@ -126,13 +129,17 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
     if (hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
     (void)hipFree(ctx->offsets);
     (void)hipFree(ctx->order);
+    (void)hipFree(ctx->blockK);
     ctx->offsets = nullptr;
     ctx->order = nullptr;
+    ctx->blockK = nullptr;
     ctx->batch_cap = 0;
   }
   ctx->last_offsets.clear();   // new buffers: the layout must be copied again
+  ctx->blockK_NT = 0;
   if (hipMalloc(&ctx->offsets, (B + 1) * sizeof(int64_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   if (hipMalloc(&ctx->order, B * sizeof(int32_t)) != hipSuccess) return PIMC_ERR_NOMEM;
+  if (hipMalloc(&ctx->blockK, B * sizeof(int8_t)) != hipSuccess) return PIMC_ERR_NOMEM;
   ctx->batch_cap = B;
   return PIMC_OK;
 }
@@ -289,6 +296,7 @@ int pimc_ctx_create(pimc_ctx** out, int device) {
   }
   if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
   if (const char* e = std::getenv("PIMC_NO_GRAPHS")) c->no_graphs = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PIMC_BATCH_UNIFORM_K")) c->uniform_batch_K = std::atoi(e) != 0;
   bool ok = ensure_tilespace(c, MAX_TILES, 4) == PIMC_OK;
   int khz = 0;
   ok = ok && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0;
@@ -312,6 +320,7 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->offsets) (void)hipFree(ctx->offsets);
   if (ctx->order) (void)hipFree(ctx->order);
+  if (ctx->blockK) (void)hipFree(ctx->blockK);
   if (ctx->halo) (void)hipFree(ctx->halo);
   if (ctx->wpart) (void)hipFree(ctx->wpart);
   if (ctx->wsync) (void)hipFree(ctx->wsync);
@@ -582,9 +591,32 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     // the host vectors die at return: make sure the copies have consumed them
     if ((r = hip_ok(hipStreamSynchronize(s)))) return r;
     ctx->last_offsets.assign(b->offsets, b->offsets + B + 1);
+    ctx->blockK_NT = 0;
+  }
+  // a batch launched with 16 sites per thread runs each window with the
+  // fewest of 4, 8, 12, 16 sites per thread that NT threads hold
+  const bool perK = T == 1 && !fp64 && K == 16 && !ctx->uniform_batch_K;
+  if (perK && ctx->blockK_NT != NT) {
+    std::vector<int8_t> bk(B);
+    for (int i = 0; i < B; ++i) {
+      const int64_t Mi = Ms[order[i]];
+      int kw = 16;
+      for (int c : {4, 8, 12}) {
+        if ((int64_t)c * NT >= Mi) {
+          kw = c;
+          break;
+        }
+      }
+      bk[i] = (int8_t)kw;
+    }
+    if ((r = hip_ok(hipMemcpyAsync(ctx->blockK, bk.data(), B * sizeof(int8_t), hipMemcpyHostToDevice, s))))
+      return r;
+    if ((r = hip_ok(hipStreamSynchronize(s)))) return r;
+    ctx->blockK_NT = NT;
   }
   a.offsets = ctx->offsets;
   a.order = ctx->order;
+  a.blockK = perK ? ctx->blockK : nullptr;
   a.X = b->X;
   a.p = b->p;
   a.y = b->y;

@@ -15,6 +15,7 @@ struct SweepArgs {
   // windows: offsets == nullptr means one window of M_single + 1 sites
   const int64_t* offsets;
   const int32_t* order;  // block -> window map (nullable: identity)
+  const int8_t* blockK;  // block -> sites per thread, 4/8/12/16 (nullable: the launch's K; K = 16 launches only)
   int64_t M_single;
   void* X;
   double* p;

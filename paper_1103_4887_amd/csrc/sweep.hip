@@ -413,649 +413,38 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double
 
 }  // namespace
 
+// The sweep of one workgroup (a window, or one time tile of it) with K
+// sites per thread.  The statements live in sweep_body.inc, which forms the
+// kernel for the launch's K and, for launches of 16 sites per thread, a
+// device function for each smaller K that a window of a batch may use; the
+// kernels of every other shape are the statements alone.
+template <typename T, int K, int MAXT, bool DBG>
+__device__ __forceinline__ void sweep_body(SweepArgs a) {
+#include "sweep_body.inc"
+}
+
+// In a batch of windows of different lengths, block b runs its window with
+// blockK[b] sites per thread (4, 8, 12 or the launch's 16: the fewest that
+// its workgroup holds), so a short window's workgroup is done in proportion
+// to its length rather than as late as the longest window's.
 template <typename T, int K, int MAXT, bool DBG>
 __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
-  static_assert(K == 2 || K % 4 == 0, "K must be 2 or a multiple of 4");
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int NT = blockDim.x;
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wv = t >> 6;
-  const int NW = NT >> 6;
-
-  // block -> (window, tile): a window is split into a.tiles time tiles of
-  // S = NT K sites, one workgroup each
-  const int tiles = a.tiles;
-  const int bi = (int)blockIdx.x / tiles;
-  int tb = (int)blockIdx.x - bi * tiles;
-  // workgroups are dealt to the 8 XCDs round-robin (block b -> XCD b % 8);
-  // when the tile count allows, consecutive tiles are given consecutive
-  // blocks of one XCD, so most boundary exchanges stay inside one L2
-  if (tiles % 8 == 0 && tiles > 8) tb = (tb % 8) * (tiles / 8) + tb / 8;
-  const int win = a.order ? a.order[bi] : bi;
-  const int S = NT * K;
-  const int tile0 = tb * S;
-  const bool last_tile = tb == tiles - 1;
-  int64_t base = 0;
-  int M = (int)a.M_single;
-  if (a.offsets) {
-    base = a.offsets[win];
-    M = (int)(a.offsets[win + 1] - base - 1);
-  }
-  const uint32_t chain = a.chain_ids ? a.chain_ids[win] : a.chain_single;
-  const Key key = make_key(a.seed, chain);
-  double* P = a.p + (int64_t)win * 7;
-
-  // ---- LDS ----------------------------------------------------------------
-  T* lfirst = (T*)smem;                           // [NT][8] first site of each thread
-  T* llast = lfirst + NT * 8;                     // [NT][8] last site of each thread
-  T* lyi = llast + NT * 8;                        // [S+2][2] (y_n, I_n), n = tile0-1 .. tile0+S
-  double* lred = (double*)(lyi + 2 * (NT * K + 2));  // [4*NW][NRED] row partials
-  double* lstat = lred + NRED * 4 * NW;           // [NRED]
-  double* ldraw = lstat + NRED;                   // [32]: p_l', accept word, FP32 log u_l, current p
-  int* lcnt = (int*)(ldraw + 32);                 // [16]
-  T* lstage = (T*)(lcnt + 16);                    // [stage][4] statistics staging
-
-  Consts<T> C;
-  if constexpr (sizeof(T) == 4)
-    C = a.cf;
-  else
-    C = a.cd;
-  double pd[7];
-#pragma unroll
-  for (int l = 0; l < 7; ++l) pd[l] = P[l];
-  C.set_p(pd);
-  // one wave per SIMD leaves room for the model constants in vector
-  // registers; with two, register pressure decides otherwise
-  constexpr bool VCONST = MAXT <= 256;
-  if constexpr (VCONST) consts_in_vgprs(C);
-  T ws[4];
-  double wpar[7];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) ws[c] = VCONST ? in_vgpr((T)a.w[c]) : (T)a.w[c];
-#pragma unroll
-  for (int l = 0; l < 7; ++l) wpar[l] = a.w[4 + l];
-  const double cA = 0.5 * a.m.beta * a.m.Rd[0];
-  const bool uniform_prop = a.m.proposal == PIMC_PROP_UNIFORM;
-  const double hD = 0.5 * a.m.dt;
-
-  // observations and drive of the tile and its two halo sites -> LDS;
-  // lyb[2 n], lyb[2 n + 1] address (y_n, I_n) by global site index
-  T* lyb = lyi + 2 * (1 - tile0);
-  {
-    const T* Yw = (const T*)a.y + base;
-    const T* Iw = (const T*)a.I + base;
-    const int lo = tile0 > 0 ? tile0 - 1 : 0;
-    const int hi = min(M, tile0 + S);
-    for (int n = lo + t; n <= hi; n += NT) {
-      lyb[2 * n] = Yw[n];
-      lyb[2 * n + 1] = Iw[n];
+  if constexpr (K == 16 && sizeof(T) == 4) {
+    const int kb = a.blockK ? (int)a.blockK[blockIdx.x] : K;
+    if (kb == 4) {
+      sweep_body<T, 4, MAXT, DBG>(a);
+      return;
+    }
+    if (kb == 8) {
+      sweep_body<T, 8, MAXT, DBG>(a);
+      return;
+    }
+    if (kb == 12) {
+      sweep_body<T, 12, MAXT, DBG>(a);
+      return;
     }
   }
-
-  // ---- own sites: n = n0 + j, j < K, plus site M on the last thread when
-  //      the regular slots stop exactly at M ------------------------------
-  const int NTneed = last_tile ? (M - tile0 + K - 1) / K : NT;
-  const bool active = t < NTneed;
-  const int n0 = tile0 + t * K;
-  const bool has_extra = last_tile && (t == NTneed - 1) && (K * NTneed == M - tile0);
-  // cross-tile halo: boundary sites of each tile in global memory, slot
-  // [gt][0] the tile's first site, [gt][1] its last.  A single-tile window
-  // never touches it; neighbours that do not exist alias this tile's own
-  // slots, so every address formed is a valid one
-  const int gt = bi * tiles + tb;                 // global tile index
-  uint64_t* hfirst = (tiles > 1 && a.halo) ? (uint64_t*)a.halo + (int64_t)gt * 2 * SLOT_WORDS : (uint64_t*)lred;
-  uint64_t* hlast = (tiles > 1 && a.halo) ? hfirst + SLOT_WORDS : hfirst;
-  const uint64_t* hprev_last = tb > 0 ? hfirst - SLOT_WORDS : hlast;
-  const uint64_t* hnext_first = !last_tile ? hfirst + 2 * SLOT_WORDS : hfirst;
-  // LDS index of the extra site's (y, I): site M when this thread owns it,
-  // else the tile's first site, so that no evaluation of the expression
-  // (speculative or not) leaves the tile's LDS block
-  const int me = has_extra ? M : tile0;
-  T* Xt = (T*)a.X + (base + n0) * 4;
-  __syncthreads();
-
-  T x[K][4], F[K][4];
-  T xe[4], Fe[4];
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const bool v = active && n0 + j <= M;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) x[j][c] = v ? Xt[j * 4 + c] : C.lo[c];
-    hh_F(C, x[j], v ? lyb[2 * (n0 + j) + 1] : (T)0, F[j]);
-    if (v) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bad = bad || !(x[j][c] >= C.lo[c] && x[j][c] <= C.hi[c]);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) xe[c] = C.lo[c];
-  if (has_extra) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) xe[c] = Xt[K * 4 + c];
-  }
-  hh_F(C, xe, has_extra ? lyb[2 * me + 1] : (T)0, Fe);
-  if (has_extra) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) bad = bad || !(xe[c] >= C.lo[c] && xe[c] <= C.hi[c]);
-  }
-  if (t == 0) {
-#pragma unroll
-    for (int l = 0; l < 7; ++l) {
-      bad = bad || !__builtin_isfinite(pd[l]);
-      if ((a.m.p_mask >> l) & 1) bad = bad || !(pd[l] >= a.m.p_lo[l] && pd[l] <= a.m.p_hi[l]);
-    }
-  }
-  if (tiles > 1) {
-    // every tile learns whether any tile failed the entry check, and the
-    // boundary sites are published before the first sweep
-    if (__syncthreads_or(bad) && t == 0) atomicOr(&a.wsync[bi * 4 + 1], 1u);
-    // generation 1: the entry state of both boundary sites; after the even
-    // half-sweep of sweep it the first site is generation it + 2, after the
-    // odd half-sweep the last site is generation it + 2
-    if (t == 0) site_publish(hfirst, x[0], F[0], 1u);
-    if (t == NT - 1 && !last_tile) site_publish(hlast, x[K - 1], F[K - 1], 1u);
-    tile_barrier(&a.wsync[bi * 4], (uint32_t)tiles, a.err, a.spin_ticks);
-    bad = __hip_atomic_load(&a.wsync[bi * 4 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-  }
-  if (__syncthreads_or(bad)) {
-    if (t == 0) atomicOr(a.err, 2u);
-    return;
-  }
-  if (active) {
-    lds_put(lfirst + t * 8, x[0], F[0]);
-    lds_put(llast + t * 8, x[K - 1], F[K - 1]);
-  }
-  if (t == 0) {
-#pragma unroll
-    for (int l = 0; l < 7; ++l) ldraw[24 + l] = pd[l];
-  }
-  __syncthreads();
-  uint32_t nbar = 1;   // tile barriers passed so far (the entry barrier)
-
-  int accE = 0, accO = 0, nonfin = 0;
-  T xnx[4] = {0, 0, 0, 0};   // last thread of a tile: the next tile's first site
-  int accP[7] = {0, 0, 0, 0, 0, 0, 0};
-  T* dx_t = DBG && a.dbg_xprop ? (T*)a.dbg_xprop + (base + n0) * 4 : nullptr;
-  double* ddA_t = DBG && a.dbg_dA ? a.dbg_dA + base + n0 : nullptr;
-  uint8_t* dacc_t = DBG && a.dbg_acc ? a.dbg_acc + base + n0 : nullptr;
-
-  for (int64_t it = 0; it < a.n_sweeps; ++it) {
-    const uint64_t k = a.sweep0 + (uint64_t)it;
-    const bool last = it == a.n_sweeps - 1;
-
-    if (a.flags & PIMC_STATES) {
-      // ---- even half-sweep ----------------------------------------------
-      // accept words: block n >> 2 of the SACC stream holds word n & 3 for
-      // sites n .. n + 3; with K = 2 two threads share a block (n0 is even)
-      constexpr int KS = K < 4 ? K : 4;
-      uint32_t uodd[K / 2];
-#pragma unroll
-      for (int q = 0; q < (K + 3) / 4; ++q) {
-        const int j0 = 4 * q;
-        U4 ub{0, 0, 0, 0};
-        if (active && n0 + j0 <= M) ub = draw(key, opaque((uint32_t)((n0 + j0) >> 2)), k, TAG_SACC);
-        uint32_t ueven[2];
-        if constexpr (K >= 4) {
-          ueven[0] = ub.x;
-          ueven[1] = ub.z;
-          uodd[2 * q] = ub.y;
-          uodd[2 * q + 1] = ub.w;
-        } else {
-          const bool upper = (n0 & 2) != 0;
-          ueven[0] = upper ? ub.z : ub.x;
-          ueven[1] = 0u;
-          uodd[0] = upper ? ub.w : ub.y;
-        }
-#pragma unroll
-        for (int jj = 0; jj < KS; jj += 2) {
-          const int j = j0 + jj;
-          const int nn = n0 + j;
-          if (active && nn <= M) {
-            Nb<T> L, R;
-            const bool hasL = nn >= 1;
-            if (j == 0) {
-              if (hasL) {
-                if (t == 0) {   // last site of the previous tile, after its odd half-sweep
-                  site_fetch(C, hprev_last, (uint32_t)it + 1, lyb[2 * nn - 1], L, a.err, a.spin_ticks);
-                } else {
-                  lds_get(C, llast + (t - 1) * 8, lyb[2 * nn - 1], L);
-                }
-              }
-            } else {
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                L.x[c] = x[j - 1][c];
-                L.F[c] = F[j - 1][c];
-              }
-            }
-            const bool hasR = nn + 1 <= M;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              R.x[c] = x[j + 1][c];
-              R.F[c] = F[j + 1][c];
-            }
-            const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
-            double dA;
-            T xp[4];
-            const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyb[2 * nn], lyb[2 * nn + 1], hasL, L,
-                                        hasR, R, nn >= 1, blk, ueven[jj >> 1], dA, xp, nonfin);
-            accE += ok;
-            if (DBG && last) {
-              if (dx_t)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) dx_t[j * 4 + c] = xp[c];
-              if (ddA_t) ddA_t[j] = dA;
-              if (dacc_t) dacc_t[j] = ok;
-            }
-          }
-        }
-      }
-      if (has_extra) {  // site M (even): left neighbour is own slot K-1, no right link
-        Nb<T> L, R;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          L.x[c] = x[K - 1][c];
-          L.F[c] = F[K - 1][c];
-          R.x[c] = xe[c];
-          R.F[c] = Fe[c];
-        }
-        const U4 blk = draw(key, opaque((uint32_t)M), k, TAG_SITE);
-        const U4 ub = draw(key, opaque((uint32_t)(M >> 2)), k, TAG_SACC);
-        const uint32_t uM = (M & 2) ? ub.z : ub.x;   // M is even
-        double dA;
-        T xp[4];
-        const bool ok = site_update(C, ws, uniform_prop, xe, Fe, lyb[2 * me], lyb[2 * me + 1], true, L, false, R,
-                                    true, blk, uM, dA, xp, nonfin);
-        accE += ok;
-        if (DBG && last) {
-          if (dx_t)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) dx_t[K * 4 + c] = xp[c];
-          if (ddA_t) ddA_t[K] = dA;
-          if (dacc_t) dacc_t[K] = ok;
-        }
-      }
-      if (active) lds_put(lfirst + t * 8, x[0], F[0]);
-      if (tiles > 1 && t == 0) site_publish(hfirst, x[0], F[0], (uint32_t)it + 2);
-      __syncthreads();
-
-      // ---- odd half-sweep -----------------------------------------------
-#pragma unroll
-      for (int j = 1; j < K; j += 2) {
-        const int nn = n0 + j;
-        if (active && nn <= M) {
-          Nb<T> L, R;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            L.x[c] = x[j - 1][c];
-            L.F[c] = F[j - 1][c];
-          }
-          const bool hasR = nn + 1 <= M;
-          if (j == K - 1) {
-            if (hasR) {
-              if (has_extra) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                  R.x[c] = xe[c];
-                  R.F[c] = Fe[c];
-                }
-              } else if (t == NT - 1) {   // first site of the next tile, after its even half-sweep
-                site_fetch(C, hnext_first, (uint32_t)it + 2, lyb[2 * nn + 3], R, a.err, a.spin_ticks);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) xnx[c] = R.x[c];   // kept for the link statistics
-              } else {
-                lds_get(C, lfirst + (t + 1) * 8, lyb[2 * nn + 3], R);
-              }
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              R.x[c] = x[j + 1][c];
-              R.F[c] = F[j + 1][c];
-            }
-          }
-          const U4 blk = draw(key, opaque((uint32_t)nn), k, TAG_SITE);
-          double dA;
-          T xp[4];
-          const bool ok = site_update(C, ws, uniform_prop, x[j], F[j], lyb[2 * nn], lyb[2 * nn + 1], true, L,
-                                      hasR, R, true, blk, uodd[j >> 1], dA, xp, nonfin);
-          accO += ok;
-          if (DBG && last) {
-            if (dx_t)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) dx_t[j * 4 + c] = xp[c];
-            if (ddA_t) ddA_t[j] = dA;
-            if (dacc_t) dacc_t[j] = ok;
-          }
-        }
-      }
-      if (active) lds_put(llast + t * 8, x[K - 1], F[K - 1]);
-      if (tiles > 1 && t == NT - 1 && !last_tile) site_publish(hlast, x[K - 1], F[K - 1], (uint32_t)it + 2);
-    }
-
-    if (a.flags & PIMC_PARAMS) {
-      // ---- random numbers of the parameter moves (path independent), spread
-      //      over the waves: wave w, lane i draws for parameter w + i NW;
-      //      the proposed value and its box test are formed here too (a move
-      //      of p_l changes no other p_j, so p_l before its move is the value
-      //      at the start of the section).  With time tiles this work fills
-      //      the wait for the other tiles' partial sums ----------------------
-      auto param_draws = [&]() {
-        const int l = wv + lane * NW;
-        if (lane * NW < 7 && l < 7) {
-          const U4 b = draw(key, opaque((uint32_t)l), k, TAG_PARAM);
-          double z;
-          if (uniform_prop) {
-            z = Math<double>::uniform_pm1(b.x);
-          } else if constexpr (sizeof(T) == 4) {
-            float z0, z1;
-            Math<float>::box_muller(b.x, b.y, z0, z1);
-            z = (double)z0;
-          } else {
-            double z1;
-            Math<double>::box_muller(b.x, b.y, z, z1);
-          }
-          // parameter-indexed values by selects (no dynamically indexed
-          // register or argument arrays)
-          double lo = 0.0, hi = 0.0;
-#pragma unroll
-          for (int q = 0; q < 7; ++q) {
-            lo = q == l ? a.m.p_lo[q] : lo;
-            hi = q == l ? a.m.p_hi[q] : hi;
-          }
-          const double pl = ldraw[24 + l] + a.w[4 + l] * z;
-          const bool inbox = pl >= lo && pl <= hi;
-          ldraw[l] = inbox ? pl : __builtin_nan("");
-          ldraw[16 + l] = ::log(u01_d(b.z));
-        }
-      };
-      if (tiles == 1) param_draws();
-      // ---- sufficient statistics over the links of the odd sites ----------
-      double th[7];
-      theta_of(pd, th);
-      double st[NRED];
-#pragma unroll
-      for (int i = 0; i < NRED; ++i) st[i] = 0.0;
-      if (active) {
-        Feat fl = feat_of(x[0], lyb[2 * n0 + 1]);
-#pragma unroll
-        for (int j = 1; j < K; j += 2) {
-          const int nn = n0 + j;
-          if (nn <= M) {
-            const Feat fc = feat_of(x[j], lyb[2 * nn + 1]);
-            link_stats(th, hD, fl, fc, st);
-            if (nn + 1 <= M) {
-              Feat fr;
-              if (j == K - 1) {
-                if (has_extra) {
-                  fr = feat_of(xe, lyb[2 * me + 1]);
-                } else {
-                  // next thread's first site, or the next tile's: read during
-                  // the odd half-sweep when sites moved, else the entry
-                  // publication, which is then current
-                  T xr[4];
-                  if (t == NT - 1 && (a.flags & PIMC_STATES)) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) xr[c] = xnx[c];
-                  } else if (t == NT - 1) {
-                    Nb<T> nb;
-                    site_fetch(C, hnext_first, 1u, lyb[2 * nn + 3], nb, a.err, a.spin_ticks);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) xr[c] = nb.x[c];
-                  } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) xr[c] = lfirst[(t + 1) * 8 + c];
-                  }
-                  fr = feat_of(xr, lyb[2 * nn + 3]);
-                }
-              } else {
-                fr = feat_of(x[j + 1], lyb[2 * nn + 3]);
-              }
-              link_stats(th, hD, fc, fr, st);
-              fl = fr;
-            }
-          }
-        }
-      }
-      // ---- block reduction: rows of 16 lanes with DPP, then a fixed-order
-      //      sum of the row partials through LDS --------------------------
-#pragma unroll
-      for (int i = 0; i < NRED; ++i) st[i] = row_sum(st[i]);
-      if ((lane & 15) == 15) {
-#pragma unroll
-        for (int i = 0; i < NRED; ++i) lred[(wv * 4 + (lane >> 4)) * NRED + i] = st[i];
-      }
-      __syncthreads();
-      if (t < NRED) {
-        // row partials laid out [row][value]: consecutive threads read
-        // consecutive words (no bank conflicts)
-        const double* row = lred + t;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int q = 0; q < 4 * NW; q += 4) {
-          s0 += row[q * NRED];
-          s1 += row[(q + 1) * NRED];
-          s2 += row[(q + 2) * NRED];
-          s3 += row[(q + 3) * NRED];
-        }
-        lstat[t] = (s0 + s1) + (s2 + s3);
-      }
-      __syncthreads();
-      if (tiles > 1) {
-        // all-reduce over the window's tiles: partials in a double buffer,
-        // summed in tile order by every tile (identical results everywhere)
-        // every partial value as two generation words, double-buffered by
-        // the parity of the barrier count
-        uint64_t* wp = (uint64_t*)a.wpart +
-                       ((int64_t)(nbar & 1) * a.ngroups * tiles + (int64_t)bi * tiles) * (2 * NRED);
-        ++nbar;
-        for (int i = t; i < 2 * NRED; i += NT) {   // 70 words; a tile may have 64 threads
-          const uint64_t b = __builtin_bit_cast(uint64_t, lstat[i >> 1]);
-          gw_store(wp + tb * 2 * NRED + i, gen_word(nbar, (i & 1) ? (uint32_t)(b >> 32) : (uint32_t)b));
-        }
-        // the parameter proposals are drawn while the other tiles' partials
-        // are on their way
-        param_draws();
-        // NRED x tiles partials: thread t sums tiles q = t / NRED, + NSEG, ...
-        // for value t % NRED with all loads in flight, then NSEG segment sums
-        // are combined in segment order (fixed for a given launch shape)
-        {
-          const int NSEG = NT / NRED;
-          const int v = t % NRED, sg = t / NRED;
-          if (sg < NSEG) {
-            double acc = 0.0;
-            for (int q0 = sg; q0 < tiles; q0 += 8 * NSEG) {
-              const uint64_t* src[16];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                const int q = q0 + u * NSEG < tiles ? q0 + u * NSEG : tb;   // absent: own words, ignored
-                src[2 * u] = wp + q * 2 * NRED + 2 * v;
-                src[2 * u + 1] = src[2 * u] + 1;
-              }
-              uint64_t w[16];
-              gw_wait<16>(src, w, nbar, a.err, a.spin_ticks);
-              double vals[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                const uint64_t b = ((uint64_t)(uint32_t)w[2 * u + 1] << 32) | (uint32_t)w[2 * u];
-                vals[u] = q0 + u * NSEG < tiles ? __builtin_bit_cast(double, b) : 0.0;
-              }
-#pragma unroll
-              for (int u = 0; u < 8; ++u) acc += vals[u];
-            }
-            lred[sg * NRED + v] = acc;
-          }
-          __syncthreads();
-          if (t < NRED) {
-            double acc = 0.0;
-            for (int q = 0; q < NSEG; ++q) acc += lred[q * NRED + t];
-            lstat[t] = acc;
-          }
-        }
-        __syncthreads();
-      }
-      // ---- sequential parameter moves, evaluated identically by every
-      //      wave (no broadcast and no further barrier needed) ---------------
-      {
-        double s7[7], G[28], zz[7], lw[7];
-#pragma unroll
-        for (int l = 0; l < 7; ++l) {
-          s7[l] = lstat[l];
-          zz[l] = ldraw[l];
-          lw[l] = ldraw[16 + l];
-        }
-#pragma unroll
-        for (int i = 0; i < 28; ++i) G[i] = lstat[7 + i];
-        bool changed = false;
-        const bool rec = last && t == 0 && tb == 0;
-        param_move<0, DBG>(a, zz[0], lw[0], cA, pd, s7, G, changed, accP[0], nonfin, rec, win);
-        param_move<1, DBG>(a, zz[1], lw[1], cA, pd, s7, G, changed, accP[1], nonfin, rec, win);
-        param_move<2, DBG>(a, zz[2], lw[2], cA, pd, s7, G, changed, accP[2], nonfin, rec, win);
-        param_move<3, DBG>(a, zz[3], lw[3], cA, pd, s7, G, changed, accP[3], nonfin, rec, win);
-        param_move<4, DBG>(a, zz[4], lw[4], cA, pd, s7, G, changed, accP[4], nonfin, rec, win);
-        param_move<5, DBG>(a, zz[5], lw[5], cA, pd, s7, G, changed, accP[5], nonfin, rec, win);
-        param_move<6, DBG>(a, zz[6], lw[6], cA, pd, s7, G, changed, accP[6], nonfin, rec, win);
-        if (changed) {
-          if (t == 0) {
-#pragma unroll
-            for (int l = 0; l < 7; ++l) ldraw[24 + l] = pd[l];
-          }
-          C.set_p(pd);
-          if constexpr (VCONST) {
-#pragma unroll
-            for (int l = 0; l < 7; ++l) C.p[l] = in_vgpr(C.p[l]);
-          }
-#pragma unroll
-          for (int j = 0; j < K; ++j) F[j][0] = hh_FV(C, x[j][0], x[j][1], x[j][2], x[j][3], lyb[2 * (n0 + j) + 1]);
-          Fe[0] = hh_FV(C, xe[0], xe[1], xe[2], xe[3], has_extra ? lyb[2 * me + 1] : (T)0);
-        }
-      }
-    } else {
-      __syncthreads();
-    }
-
-    // ---- statistics ------------------------------------------------------
-    if (a.ptrace && t == 0 && tb == 0) {
-#pragma unroll
-      for (int l = 0; l < 7; ++l) a.ptrace[(int64_t)win * a.n_sweeps * 7 + it * 7 + l] = pd[l];
-    }
-    if (a.sum && (int64_t)k >= a.burn && ((int64_t)k - a.burn) % a.stride == 0) {
-      // stage the path through LDS so that the FP64 read-modify-write of the
-      // moment sums is coalesced (consecutive lanes, consecutive addresses)
-      const T* xr = (const T*)a.xref + base * 4;
-      double* su = a.sum + base * 4;
-      double* sq = a.sumsq ? a.sumsq + base * 4 : nullptr;
-      // batch of this sample: the i-th of the call's nsamp samples belongs
-      // to batch floor(i nbatch / nsamp)
-      double* bt = nullptr;
-      if (a.batch) {
-        const int64_t si = ((int64_t)k - a.kfirst) / a.stride;
-        bt = a.batch + (si * a.nbatch / a.nsamp) * a.bslice + base * 4;
-      }
-      const int Sst = a.stage;
-      const int hi_site = last_tile ? M : tile0 + S - 1;   // this tile's sites only
-      for (int c0 = tile0; c0 <= hi_site; c0 += Sst) {
-        if (active) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            const int n = n0 + j;
-            if (n <= M && n >= c0 && n < c0 + Sst) {
-#pragma unroll
-              for (int c = 0; c < 4; ++c) lstage[(n - c0) * 4 + c] = x[j][c];
-            }
-          }
-          if (has_extra && M >= c0 && M < c0 + Sst) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) lstage[(M - c0) * 4 + c] = xe[c];
-          }
-        }
-        __syncthreads();
-        const int cnt = 4 * min(Sst, hi_site + 1 - c0);
-        // eight independent elements per round: all loads are in flight
-        // before the first add, so the loop is bandwidth- not latency-bound
-        for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
-          double dv[8], s1[8], s2[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * NT;
-            const int64_t g = (int64_t)c0 * 4 + e;
-            dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
-            s1[u] = e < cnt ? su[g] : 0.0;
-            s2[u] = (e < cnt && sq) ? sq[g] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * NT;
-            const int64_t g = (int64_t)c0 * 4 + e;
-            if (e < cnt) {
-              su[g] = s1[u] + dv[u];
-              if (sq) sq[g] = s2[u] + dv[u] * dv[u];
-            }
-          }
-        }
-        // the batch sums in a pass of their own, so that runs without them
-        // keep the registers of the pass above
-        if (bt) {
-          for (int e0 = t; e0 < cnt; e0 += 8 * NT) {
-            double dv[8], s3[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int e = e0 + u * NT;
-              const int64_t g = (int64_t)c0 * 4 + e;
-              dv[u] = e < cnt ? (double)lstage[e] - (double)xr[g] : 0.0;
-              s3[u] = e < cnt ? bt[g] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int e = e0 + u * NT;
-              if (e < cnt) bt[(int64_t)c0 * 4 + e] = s3[u] + dv[u];
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-
-  // ---- write back ---------------------------------------------------------
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    if (active && n0 + j <= M) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) Xt[j * 4 + c] = x[j][c];
-    }
-  }
-  if (has_extra) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Xt[K * 4 + c] = xe[c];
-  }
-  if (t == 0 && tb == 0) {
-#pragma unroll
-    for (int l = 0; l < 7; ++l) P[l] = pd[l];
-  }
-  // ---- acceptance counters ----------------------------------------------
-  __syncthreads();
-  if (t < 16) lcnt[t] = 0;
-  __syncthreads();
-  if (accE) atomicAdd(&lcnt[0], accE);
-  if (accO) atomicAdd(&lcnt[1], accO);
-  if (nonfin && lane != 0) atomicAdd(&lcnt[9], nonfin);
-  if (t == 0 && tb == 0) {
-    // parameter counts (and their non-finite count) are identical in every
-    // wave and every tile; lane 0 of wave 0 of tile 0 reports them once
-#pragma unroll
-    for (int l = 0; l < 7; ++l) lcnt[2 + l] += accP[l];
-    if (nonfin) atomicAdd(&lcnt[9], nonfin);
-  }
-  __syncthreads();
-  if (t == 0) {
-    if (a.acc) {
-      for (int i = 0; i < PIMC_NACC; ++i)
-        if (lcnt[i]) atomicAdd((unsigned long long*)&a.acc[(int64_t)win * PIMC_NACC + i], (unsigned long long)lcnt[i]);
-    }
-    if (lcnt[9]) atomicOr(a.err, 1u);
-  }
+#include "sweep_body.inc"
 }
 
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {

@@ -569,3 +569,50 @@ def test_long_fp64_window_auto_tiled_lockstep(ctx):
     if ties == 0:
         np.testing.assert_allclose(win.X.cpu().numpy(), Xo, rtol=1e-13, atol=1e-13)
         np.testing.assert_allclose(win.p.cpu().numpy(), po, rtol=1e-14)
+
+
+def test_batch_per_window_sites_per_thread(ctx, monkeypatch):
+    """A batch launched with 16 sites per thread runs each window with the
+    fewest of 4, 8, 12, 16 sites per thread its workgroup holds (here
+    448 threads: 4, 4, 8, 12, 16, 16).  Every window's chain and statistics
+    equal its run in the batch launched with 16 sites per thread for all
+    windows, and its own single-window run (X bit for bit; p within 1e-14)."""
+    Ms = [300, 1500, 2500, 4500, 6100, 7000]
+    probs = [W.make_hh_problem(M, 0.02, 700 + i, require_spike=False) for i, M in enumerate(Ms)]
+    spec = probs[0].model
+    chains = [21 + i for i in range(len(Ms))]
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+    n = 6
+    monkeypatch.setenv("PIMC_BATCH_UNIFORM_K", "1")
+    c2 = P.Context(0)
+    monkeypatch.delenv("PIMC_BATCH_UNIFORM_K")
+    outs = []
+    try:
+        for c in (ctx, c2):
+            c.set_tile(16)
+            batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                                       [q.I for q in probs], chains, "fp32")
+            dev = batch.X.device
+            st = P.SweepStats(sum=torch.zeros(batch.X.shape, dtype=torch.float64, device=dev),
+                              xref=batch.X.clone(),
+                              ptrace=torch.zeros((len(Ms), n, 7), dtype=torch.float64, device=dev),
+                              acc=torch.zeros((len(Ms), 10), dtype=torch.int64, device=dev), burn=2)
+            print(f"batch Ms={Ms} {'per-window' if c is ctx else 'uniform'} sites per thread", flush=True)
+            P.pimc_run_batch(c, spec, batch, seed=31, sweep0=5, w=w, n_sweeps=n, stats=st)
+            assert c.sync() == 0
+            outs.append((batch, st))
+            c.set_tile(0)
+        (b1, s1), (b2, s2) = outs
+        np.testing.assert_array_equal(b1.X.cpu().numpy(), b2.X.cpu().numpy())
+        np.testing.assert_allclose(b1.p.cpu().numpy(), b2.p.cpu().numpy(), rtol=1e-14)
+        np.testing.assert_array_equal(s1.acc.cpu().numpy(), s2.acc.cpu().numpy())
+        np.testing.assert_allclose(s1.sum.cpu().numpy(), s2.sum.cpu().numpy(), rtol=1e-12, atol=1e-12)
+        for i, q in enumerate(probs):
+            win = P.Window.from_arrays(q.X0, q.p0, q.y, q.I, "fp32")
+            P.pimc_sweep(ctx, spec, win, seed=31, chain=chains[i], sweep0=5, w=w, n_sweeps=n)
+            assert ctx.sync() == 0
+            a, b = int(b1.offsets[i]), int(b1.offsets[i + 1])
+            np.testing.assert_array_equal(b1.X[a:b].cpu().numpy(), win.X.cpu().numpy())
+            np.testing.assert_allclose(b1.p[i].cpu().numpy(), win.p.cpu().numpy(), rtol=1e-14)
+    finally:
+        c2.close()

@@ -36,7 +36,7 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 # WRITE_SIZE runs calibrated against a plain copy (profiles/ holds the
 # summary).  They belong to one version of the kernel source: when the source
 # hash differs, the traffic is reported as unknown.
-TRAFFIC = {"sweep_hip_sha256": "c61e60fdf65a398368c984d6915481763d7deeedae10b1aea267ded93c2daf38",
+TRAFFIC = {"sweep_source_sha256": "c61e60fdf65a398368c984d6915481763d7deeedae10b1aea267ded93c2daf38",
            "launch": (2, 16), "fetch_bytes_per_sweep": 77.7e3, "write_bytes_per_sweep": 16.6e3}
 
 
@@ -61,12 +61,19 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_per_launch(shape, sweeps: int):
+def kernel_source_sha256() -> str:
+    """sha256 over the sweep kernel's source files (sweep.hip, then sweep_body.inc)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1103_4887_amd", "csrc", "sweep.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if sha != TRAFFIC["sweep_hip_sha256"] or tuple(shape[:2]) != TRAFFIC["launch"]:
+    h = hashlib.sha256()
+    for name in ("sweep.hip", "sweep_body.inc"):
+        with open(os.path.join(ROOT, "paper_1103_4887_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(shape, sweeps: int):
+    sha = kernel_source_sha256()
+    if sha != TRAFFIC["sweep_source_sha256"] or tuple(shape[:2]) != TRAFFIC["launch"]:
         return None
     return (TRAFFIC["fetch_bytes_per_sweep"] + TRAFFIC["write_bytes_per_sweep"]) * sweeps
 

@@ -228,7 +228,10 @@ int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path,
  * w (device FP64 [11]); window w uses Philox chain id batch->chain[w] and
  * sweep indices sweep0 .. sweep0+n-1, so a window's chain equals its own
  * pimc_sweep run.  Windows run longest first, one workgroup each, or as
- * time tiles (see pimc_set_sweep_tiles).  The untiled launch is recorded
+ * time tiles (see pimc_set_sweep_tiles).  When the launch gives 16 sites per
+ * thread (FP32, untiled), each window runs with the fewest of 4, 8, 12, 16
+ * sites per thread that the workgroup holds, so short windows finish early
+ * (environment PIMC_BATCH_UNIFORM_K=1 keeps 16 for all).  The untiled launch is recorded
  * once per launch shape into a HIP graph and replayed with each call's
  * arguments; the batch layout (offsets) is copied to the device, with a
  * wait, only when it differs from the previous call's, so repeated calls on

@@ -36,8 +36,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 # WRITE_SIZE runs calibrated against a plain copy (profiles/ holds the
 # summary).  They belong to one version of the kernel source: when the source
 # hash differs, the traffic is reported as unknown.
-TRAFFIC = {"sweep_source_sha256": "c61e60fdf65a398368c984d6915481763d7deeedae10b1aea267ded93c2daf38",
-           "launch": (2, 16), "fetch_bytes_per_sweep": 77.7e3, "write_bytes_per_sweep": 16.6e3}
+TRAFFIC = {"sweep_source_sha256": "6a7bfdd18f5d7d9fe4148efa3248dfdb1b48915261d53343bf3f3ea8c45d3b42",
+           "launch": (2, 16), "fetch_bytes_per_sweep": 77.8e3, "write_bytes_per_sweep": 16.6e3}
 
 
 def parse():

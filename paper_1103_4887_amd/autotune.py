@@ -79,13 +79,13 @@ _BCACHE: Dict[Tuple, Tuple[int, int, float]] = {}
 
 def batch_candidates(sizes, prec: str) -> Iterable[Tuple[int, int]]:
     """(K, T) pairs for a batch: one workgroup per window with each K, and
-    time tiles when every window is long enough to be cut (the library falls
-    back to one workgroup per window where the windows need different tile
-    counts, so such candidates simply time that fallback)."""
+    time tiles for batches of equal windows long enough to be cut (the
+    library tiles a batch only when every window needs the same number of
+    tiles; windows of different lengths run one workgroup each)."""
     yield (0, 1)
     for K in ((4,) if prec == "fp64" else (4, 8, 16)):
         yield (K, 1)
-    if prec == "fp64":
+    if prec == "fp64" or min(sizes) != max(sizes):
         return
     lo = int(min(sizes))
     for T in (2, 4, 8, 16):

@@ -36,6 +36,7 @@ from .action import delta_params, delta_site
 
 STATES = 1
 PARAMS = 2
+GIBBS = 4      # parameters drawn from their exact conditionals (see gibbs.py)
 
 ACC_EVEN, ACC_ODD, ACC_PARAM0, ACC_NONFINITE = 0, 1, 2, 9
 N_ACC = 10
@@ -74,6 +75,53 @@ class Stats:
         self.batch = np.zeros((self.nbatch, self.M + 1, self.D))
         self.ptrace = np.zeros((self.n_sweeps, self.Np))
         self.acc = np.zeros(N_ACC, dtype=np.int64)
+
+
+@dataclass
+class InitPhase:
+    """State of the initialization phase of Section 4.2, carried across calls.
+
+    Simulated annealing: the dynamical term of the action carries a
+    multiplier beta; the first sweep of the run uses beta0 and beta is
+    multiplied by f_beta = (1/beta0)**(1/n_cool) (eq. fbeta) after every
+    sweep until it reaches 1 (it is capped there).
+
+    Step sizes: every n_skip-th sweep of the run (k + 1 a multiple of
+    n_skip) while k < n_init, every step size is multiplied by
+    1 + alpha (N_acc / n_skip - f_acc), N_acc being the accepted changes of
+    that path component over the past n_skip sweeps (Section 4.2, the rule
+    for Delta_i), and the counts restart.  Reading: the D components of a
+    site move jointly with one decision (Fig. 1), so they share N_acc and
+    their steps keep the ratios of the base widths: the step of component a
+    at site n is w_state[a] * site_scale[n].  Each sampled parameter has
+    its own step w_param[l] and count.
+    """
+
+    beta0: float
+    n_cool: int
+    n_init: int
+    n_skip: int
+    f_acc: float = 0.23
+    alpha: float = 0.02
+    beta: float = float("nan")                      # beta of the next sweep
+    site_scale: Optional[np.ndarray] = None        # (M+1,)
+    w_param: Optional[np.ndarray] = None           # (Np,)
+    cnt_site: Optional[np.ndarray] = None          # (M+1,) int
+    cnt_param: Optional[np.ndarray] = None         # (Np,) int
+
+    def start(self, M, w_param):
+        """Fresh state for a run: beta = beta0, unit site scales, the given
+        parameter steps, zero counts."""
+        self.beta = float(self.beta0)
+        self.site_scale = np.ones(M + 1)
+        self.w_param = np.array(w_param, dtype=np.float64)
+        self.cnt_site = np.zeros(M + 1, dtype=np.int64)
+        self.cnt_param = np.zeros(len(self.w_param), dtype=np.int64)
+        return self
+
+    @property
+    def f_beta(self):
+        return (1.0 / self.beta0) ** (1.0 / self.n_cool)
 
 
 @dataclass
@@ -126,7 +174,7 @@ def _in_box(x, lo, hi):
 
 
 def color_update(spec, X, y, I, p, k, color, w_state, seed, chain, acc=None,
-                 order=None, debug: Optional[Debug] = None):
+                 order=None, debug: Optional[Debug] = None, site_scale=None, cnt_site=None):
     """Update every site of one parity (in place).
 
     order=None evaluates the colour at once (legal because same-parity sites
@@ -136,7 +184,10 @@ def color_update(spec, X, y, I, p, k, color, w_state, seed, chain, acc=None,
     M = X.shape[0] - 1
     ns = np.arange(color, M + 1, 2)
     z, u = site_draws(spec, seed, chain, k, ns)
-    xprop = X[ns] + np.asarray(w_state)[None, :] * z
+    w = np.asarray(w_state)[None, :]
+    if site_scale is not None:     # per-site steps of the initialization phase
+        w = w * site_scale[ns][:, None]
+    xprop = X[ns] + w * z
     lo = np.asarray(spec.x_lo)
     hi = np.asarray(spec.x_hi)
     inbox = _in_box(xprop, lo, hi)
@@ -158,6 +209,8 @@ def color_update(spec, X, y, I, p, k, color, w_state, seed, chain, acc=None,
     if acc is not None:
         acc[ACC_EVEN + color] += int(accept.sum())
         acc[ACC_NONFINITE] += int((inbox & ~np.isfinite(dA)).sum())
+    if cnt_site is not None:
+        cnt_site[ns] += accept
     if debug is not None:
         debug.xprop[ns] = xprop
         debug.dA[ns] = dA
@@ -167,7 +220,7 @@ def color_update(spec, X, y, I, p, k, color, w_state, seed, chain, acc=None,
 
 
 def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
-                debug: Optional[Debug] = None):
+                debug: Optional[Debug] = None, cnt_param=None):
     """Sequential Metropolis moves of the sampled parameters (in place on p)."""
     lo = np.asarray(spec.p_lo)
     hi = np.asarray(spec.p_hi)
@@ -188,6 +241,8 @@ def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
             p[l] = pp[l]
             if acc is not None:
                 acc[ACC_PARAM0 + l] += 1
+            if cnt_param is not None:
+                cnt_param[l] += 1
         if debug is not None:
             debug.pprop[l] = pp[l]
             debug.pdA[l] = dA
@@ -197,20 +252,32 @@ def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
 
 def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
         flags=STATES | PARAMS, stats: Optional[Stats] = None,
-        debug: Optional[Debug] = None, order_rng: Optional[np.random.Generator] = None):
+        debug: Optional[Debug] = None, order_rng: Optional[np.random.Generator] = None,
+        init: Optional[InitPhase] = None):
     """n_sweeps sweeps k = sweep0 .. sweep0 + n_sweeps - 1, in place on X, p.
 
     debug, if given, is filled for the last sweep of the call.
     order_rng, if given, visits the sites of each colour in a random order.
+    flags & GIBBS draws the parameters from their exact conditionals
+    (gibbs.param_gibbs) instead of Metropolis moves.
+    init, if given, runs the initialization phase of Section 4.2 (see
+    InitPhase; its state is updated in place and w_param is then unused):
+    sweep k uses the annealed multiplier init.beta in place of spec.beta.
     """
+    from dataclasses import replace
+
+    from .gibbs import param_gibbs
     M = X.shape[0] - 1
     acc = stats.acc if stats is not None else None
     if stats is not None:
         stride = max(stats.stride, 1)
         sampled = [k >= stats.burn and (k - stats.burn) % stride == 0 for k in range(sweep0, sweep0 + n_sweeps)]
         ns, si = sum(sampled), 0
+    base_spec = spec
     for i in range(n_sweeps):
         k = sweep0 + i
+        if init is not None:
+            spec = replace(base_spec, beta=init.beta)
         dbg = debug if (debug is not None and i == n_sweeps - 1) else None
         if dbg is not None:
             D = X.shape[1]
@@ -228,9 +295,26 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
                 if order_rng is not None:
                     order = order_rng.permutation(len(range(color, M + 1, 2)))
                 color_update(spec, X, y, I, p, k, color, w_state, seed, chain,
-                             acc=acc, order=order, debug=dbg)
-        if flags & PARAMS:
-            param_moves(spec, X, I, p, k, w_param, seed, chain, acc=acc, debug=dbg)
+                             acc=acc, order=order, debug=dbg,
+                             site_scale=init.site_scale if init is not None else None,
+                             cnt_site=init.cnt_site if init is not None else None)
+        if flags & PARAMS and flags & GIBBS:
+            param_gibbs(spec, X, I, p, k, seed, chain, acc=acc, debug=dbg)
+        elif flags & PARAMS:
+            param_moves(spec, X, I, p, k, init.w_param if init is not None else w_param, seed, chain,
+                        acc=acc, debug=dbg, cnt_param=init.cnt_param if init is not None else None)
+        if init is not None:
+            # Section 4.2: beta grows by f_beta after every sweep up to 1; the
+            # steps follow the acceptance of the past n_skip sweeps, every
+            # n_skip-th sweep of the initialization phase
+            init.beta = min(1.0, init.beta * init.f_beta)
+            if k < init.n_init and (k + 1) % init.n_skip == 0:
+                init.site_scale *= 1.0 + init.alpha * (init.cnt_site / init.n_skip - init.f_acc)
+                on = np.array([(base_spec.p_mask >> l) & 1 for l in range(len(p))], dtype=bool)
+                upd = 1.0 + init.alpha * (init.cnt_param / init.n_skip - init.f_acc)
+                init.w_param[on] *= upd[on]
+                init.cnt_site[:] = 0
+                init.cnt_param[:] = 0
         if stats is not None:
             stats.ptrace[i] = p
             if sampled[i]:

@@ -90,6 +90,20 @@ def delta_params(spec, X, I, p, pprop):
     return 0.5 * spec.beta * math.fsum(terms.tolist())
 
 
+def delta_kinetic(spec, X, I, p, gates_new):
+    """A(X, p; gates') - A(X, p; gates) by the direct sum over every link.
+
+    The gating constants of Table 1 enter only the gate equations of F
+    (Section 5.1), so only the dynamical term changes; like the parameter
+    moves of Section 4.1 the change is summed over all n = 1..M (fsum)."""
+    X = np.asarray(X, dtype=np.float64)
+    Rd = np.asarray(spec.Rd, dtype=np.float64)
+    e0 = eps(model_for(spec), X, I, p, spec.dt)
+    e1 = eps(model_for(spec.with_(gates=tuple(tuple(g) for g in gates_new))), X, I, p, spec.dt)
+    terms = (Rd[None, :] * (e1 * e1 - e0 * e0)).ravel()
+    return 0.5 * spec.beta * math.fsum(terms.tolist())
+
+
 def grad(spec, X, y, I, p):
     """Analytic gradient (dA/dX (M+1, D), dA/dp (Np,)).
 

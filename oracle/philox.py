@@ -39,6 +39,7 @@ TAG_PARAM = 3
 TAG_MOM = 4
 TAG_PMOM = 5
 TAG_HACC = 6
+TAG_KIN = 7      # moves of the Table 1 kinetic constants
 
 TWO_M32 = 2.0 ** -32
 

@@ -32,11 +32,12 @@ from typing import Optional
 import numpy as np
 
 from . import philox as ph
-from .action import delta_params, delta_site
+from .action import delta_kinetic, delta_params, delta_site
 
 STATES = 1
 PARAMS = 2
 GIBBS = 4      # parameters drawn from their exact conditionals (see gibbs.py)
+KINETIC = 8    # the Table 1 constants of the gates sampled too (kinetic_moves)
 
 ACC_EVEN, ACC_ODD, ACC_PARAM0, ACC_NONFINITE = 0, 1, 2, 9
 N_ACC = 10
@@ -136,6 +137,9 @@ class Debug:
     pdA: Optional[np.ndarray] = None       # (Np,)
     pu: Optional[np.ndarray] = None        # (Np,)
     paccept: Optional[np.ndarray] = None   # (Np,) bool
+    kprop: Optional[np.ndarray] = None     # (12,) proposed Table 1 constants
+    kdA: Optional[np.ndarray] = None
+    kaccept: Optional[np.ndarray] = None
 
 
 def accepts(u, dA):
@@ -250,10 +254,47 @@ def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
             debug.paccept[l] = ok
 
 
+def kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=None, debug=None):
+    """Sequential Metropolis moves of the sampled Table 1 constants (in place
+    on kin, shape (12,) in the order (m, h, n) x (V_a, dV_a, tau0, tau1)).
+
+    Section 5.1 notes that all the constants of the model can be estimated
+    with the same method as p.  They enter the gate equations nonlinearly,
+    so each move is the paper's direct full pass (Section 4.1): propose
+    kin_i + w_i z (Philox KIN block of index i: z from words 0, 1, u from
+    word 2), reject outside the box k_lo/k_hi, else accept with the
+    Metropolis rule on the change of A summed over the whole path.
+    Reading: the constants move after the seven parameters, in the order
+    above.  debug, if given, gets kprop/kdA/kaccept (12,)."""
+    lo, hi = np.asarray(spec.k_lo), np.asarray(spec.k_hi)
+    for i in range(12):
+        if not (spec.k_mask >> i) & 1:
+            continue
+        b = ph.draw(seed, chain, i, k, ph.TAG_KIN)[0]
+        z = float(ph.box_muller(b[0], b[1])[0])
+        u = float(ph.uniform_open(b[2]))
+        prop = kin.copy()
+        prop[i] = kin[i] + w_kin[i] * z
+        dA, ok = np.nan, False
+        if lo[i] <= prop[i] <= hi[i]:
+            cur = spec.with_(gates=tuple(tuple(g) for g in kin.reshape(3, 4)))
+            dA = delta_kinetic(cur, X, I, p, prop.reshape(3, 4))
+            ok = bool(accepts(u, dA))
+            if not np.isfinite(dA) and acc is not None:
+                acc[ACC_NONFINITE] += 1
+        if ok:
+            kin[i] = prop[i]
+        if debug is not None:
+            debug.kprop[i] = prop[i]
+            debug.kdA[i] = dA
+            debug.kaccept[i] = ok
+
+
 def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
         flags=STATES | PARAMS, stats: Optional[Stats] = None,
         debug: Optional[Debug] = None, order_rng: Optional[np.random.Generator] = None,
-        init: Optional[InitPhase] = None):
+        init: Optional[InitPhase] = None, kin: Optional[np.ndarray] = None,
+        w_kin: Optional[np.ndarray] = None):
     """n_sweeps sweeps k = sweep0 .. sweep0 + n_sweeps - 1, in place on X, p.
 
     debug, if given, is filled for the last sweep of the call.
@@ -263,6 +304,9 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
     init, if given, runs the initialization phase of Section 4.2 (see
     InitPhase; its state is updated in place and w_param is then unused):
     sweep k uses the annealed multiplier init.beta in place of spec.beta.
+    kin (12,), if given, holds the Table 1 constants (in/out: they replace
+    spec.gates); with flags & KINETIC the constants of spec.k_mask move
+    after the parameters (kinetic_moves, steps w_kin).
     """
     from dataclasses import replace
 
@@ -278,6 +322,8 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
         k = sweep0 + i
         if init is not None:
             spec = replace(base_spec, beta=init.beta)
+        if kin is not None:
+            spec = replace(spec, gates=tuple(tuple(float(v) for v in g) for g in kin.reshape(3, 4)))
         dbg = debug if (debug is not None and i == n_sweeps - 1) else None
         if dbg is not None:
             D = X.shape[1]
@@ -289,6 +335,9 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
             dbg.pdA = np.full(len(p), np.nan)
             dbg.pu = np.full(len(p), np.nan)
             dbg.paccept = np.zeros(len(p), dtype=bool)
+            dbg.kprop = np.full(12, np.nan)
+            dbg.kdA = np.full(12, np.nan)
+            dbg.kaccept = np.zeros(12, dtype=bool)
         if flags & STATES:
             for color in (0, 1):
                 order = None
@@ -303,6 +352,8 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
         elif flags & PARAMS:
             param_moves(spec, X, I, p, k, init.w_param if init is not None else w_param, seed, chain,
                         acc=acc, debug=dbg, cnt_param=init.cnt_param if init is not None else None)
+        if kin is not None and flags & KINETIC:
+            kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=acc, debug=dbg)
         if init is not None:
             # Section 4.2: beta grows by f_beta after every sweep up to 1; the
             # steps follow the acceptance of the past n_skip sweeps, every

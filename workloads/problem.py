@@ -47,6 +47,9 @@ class ModelSpec:
     p_lo/p_hi parameter box.
     p_mask    bit l set means parameter l+1 is sampled.
     proposal  "gauss" (default) or "uniform" (Fig. 1 step 1a).
+    k_lo/k_hi box of the twelve Table 1 constants, flattened in the order
+              (m, h, n) x (V_a, dV_a, tau0, tau1).
+    k_mask    bit 4 g + c set means constant c of gate g is sampled.
     """
 
     kind: str = "hh"
@@ -61,6 +64,9 @@ class ModelSpec:
     p_hi: Tuple[float, ...] = tuple(sorted((0.5 * v, 1.5 * v))[1] for v in P_STAR)
     p_mask: int = 0x7F
     proposal: str = "gauss"
+    k_lo: Tuple[float, ...] = tuple(sorted((0.5 * v, 1.5 * v))[0] for g in GATES_MHN for v in g)
+    k_hi: Tuple[float, ...] = tuple(sorted((0.5 * v, 1.5 * v))[1] for g in GATES_MHN for v in g)
+    k_mask: int = 0
 
     @property
     def D(self) -> int:

@@ -14,14 +14,18 @@ The oracle finds the quadratic by evaluating the change of A at three points
 of the box with the direct sum over the path (Section 4.1), reads off the
 mean and variance, and draws by inversion of the truncated normal CDF with
 one uniform from the parameter's Philox block (word 0; word 2 stays the
-Metropolis accept uniform).  A conditional that is not a proper Gaussian
-(curvature not positive, or not finite) is drawn uniformly on the box.
+Metropolis accept uniform); the inversion is SciPy's truncated-normal
+quantile, which stays accurate when the box lies far out in a tail of the
+Gaussian (a path far from the data makes the conditional mean of a
+parameter sit many standard deviations outside its box).  A conditional
+that is not a proper Gaussian (curvature not positive, or not finite) is
+drawn uniformly on the box.
 """
 
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import ndtr, ndtri
+from scipy.stats import truncnorm
 
 from . import philox as ph
 from .action import delta_params
@@ -47,18 +51,11 @@ def conditional(spec, X, I, p, l):
 
 
 def truncnorm_inverse(mu, sigma, lo, hi, u):
-    """The u-quantile of N(mu, sigma^2) truncated to [lo, hi]; a tail above
-    the mean is handled through the upper-tail probabilities so that far
-    tails keep their precision."""
+    """The u-quantile (u scalar or array) of N(mu, sigma^2) truncated to
+    [lo, hi]."""
     if not np.isfinite(sigma):
-        return lo + u * (hi - lo)
-    a = (lo - mu) / sigma
-    b = (hi - mu) / sigma
-    if a >= 0.0:
-        pa, pb = ndtr(-a), ndtr(-b)               # P(Z > a) >= P(Z > b)
-        return mu - sigma * ndtri(pa - u * (pa - pb))
-    pa, pb = ndtr(a), ndtr(b)
-    return mu + sigma * ndtri(pa + u * (pb - pa))
+        return lo + np.asarray(u) * (hi - lo)
+    return truncnorm.ppf(u, (lo - mu) / sigma, (hi - mu) / sigma, loc=mu, scale=sigma)
 
 
 def gibbs_draw_uniform(seed, chain, k, l):

@@ -47,7 +47,7 @@ def _grid_moments(spec, X, I, p, l, n=20001):
 def _draw_moments(spec, X, I, p, l, n=200001):
     mu, sigma = OG.conditional(spec, X, I, p, l)
     u = (np.arange(n) + 0.5) / n
-    v = np.array([OG.truncnorm_inverse(mu, sigma, spec.p_lo[l], spec.p_hi[l], ui) for ui in u])
+    v = np.asarray(OG.truncnorm_inverse(mu, sigma, spec.p_lo[l], spec.p_hi[l], u), dtype=np.float64)
     assert (v >= spec.p_lo[l]).all() and (v <= spec.p_hi[l]).all()
     return v.mean(), v.var()
 
@@ -94,6 +94,23 @@ def test_truncated_conditional_matches_quadrature(side):
     sd = np.sqrt(v_q)
     assert abs(m_d - m_q) < 2e-3 * sd
     assert abs(v_d / v_q - 1.0) < 5e-3
+
+
+@pytest.mark.parametrize("dist", [8.0, 45.0])
+def test_far_tail_box_draws_stay_in_the_box_and_follow_the_tail(dist):
+    """A path far from the data can put the conditional mean many standard
+    deviations below the box: every draw is finite, inside the box, and
+    follows the truncated density (the mean of Z given Z > a is the inverse
+    Mills ratio phi(a) / Q(a), the box's far end adding nothing visible)."""
+    from scipy.special import erfcx
+    mu, sigma = 0.0, 1.0
+    lo, hi = dist, dist + 10.0
+    u = (np.arange(20001) + 0.5) / 20001
+    v = np.asarray(OG.truncnorm_inverse(mu, sigma, lo, hi, u), dtype=np.float64)
+    assert np.isfinite(v).all() and (v >= lo).all() and (v <= hi).all()
+    m = v.mean()
+    mills = np.sqrt(2.0 / np.pi) / erfcx(dist / np.sqrt(2.0))
+    assert abs(m - mills) < 1e-5
 
 
 def test_gibbs_sweep_uses_the_parameter_stream_and_keeps_the_path():

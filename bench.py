@@ -25,11 +25,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "path site-updates/s + param ESS/s, HMC vs plain sweep, HH M=4096, 1 GPU"
 
-# VALU lane-slots the method needs per FP32-mode site update, counted from
-# its arithmetic (see the per-unit table of the design notes): Philox 1.25
-# blocks, Box-Muller, F(x') and dF, local dA, FP64 log for the decision,
-# the parameter sufficient-statistic link, neighbour exchange.
-SLOTS_PER_SITE_UPDATE = 560
+# VALU lane-slots the method needs per FP32-mode site update (the per-unit
+# figure of the measurement plan): two Philox blocks (about 200 integer
+# slots, the 32x32->64 products at reduced rate), four Box-Muller normals,
+# F(x') with three tanh and three reciprocals, the local dA, the FP64
+# decision and the parameter sufficient-statistic terms.
+SLOTS_PER_SITE_UPDATE = 500
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 
 # HBM bytes per sweep of the benchmark shape, from rocprofv3 FETCH_SIZE and
@@ -48,7 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--config", default="c2",
                     help="c1-c3: one window; c4: the uneven batch; c5: HMC on 64 chains (default c2)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of each oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="sites per thread (0: autotune)")
     ap.add_argument("--tiles", type=int, default=-1, help="time tiles per window (-1: autotune)")
@@ -58,6 +59,8 @@ def parse():
     ap.add_argument("--cmp-chains", type=int, default=64)
     ap.add_argument("--cmp-equilibrate", type=float, default=5.0,
                     help="untimed seconds of batched sweeps that equilibrate the chains before the comparison")
+    ap.add_argument("--no-sub-blocks", dest="sub_blocks", action="store_false",
+                    help="c2 only: skip the short batched (c4) and HMC (c5) measurements")
     return ap.parse_args()
 
 
@@ -78,6 +81,70 @@ def traffic_per_launch(shape, sweeps: int):
     return (TRAFFIC["fetch_bytes_per_sweep"] + TRAFFIC["write_bytes_per_sweep"]) * sweeps
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Worker processes for the N-core oracle legs: the host cores this
+    process may use, at most 16 (the share of one GPU on the box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_worker(job):
+    """One host core: the oracle on its own window for `budget` seconds.
+    Runs in a spawned process that never touches the GPU."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    kind, prob, budget, extra = job
+    from oracle import hmc as OH
+    from oracle import sampler as OS
+
+    X, p = prob.X0.copy(), prob.p0.copy()
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget:
+        if kind == "sweep":
+            OS.run(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=0, sweep0=n, n_sweeps=1,
+                   w_state=prob.w_state, w_param=prob.w_param)
+        else:
+            eps, L, minv = extra
+            X, p, _, _ = OH.hmc_proposal(prob.model, X, p, prob.y, prob.I, seed=prob.seed, chain=0, k=n, e=eps,
+                                         L=L, minv_state=minv[:4], minv_param=minv[4:])
+        n += 1
+    wall = time.perf_counter() - t0
+    units = (prob.M + 1) * n * (1 if kind == "sweep" else extra[1])
+    return units, wall, n
+
+
+def cpu_baseline_ncore(kind: str, probs, budget_s: float, extra=None):
+    """The oracle on every host core at once (one spawned process per core,
+    each on its own window or chain); rate = all units / the longest wall."""
+    import multiprocessing as mp
+
+    ncore = host_cores()
+    jobs = [(kind, probs[i % len(probs)], budget_s, extra) for i in range(ncore)]
+    with mp.get_context("spawn").Pool(ncore) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    units = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    unit = "site-updates/s" if kind == "sweep" else "site-leapfrogs/s"
+    what = "sweeps" if kind == "sweep" else "HMC proposals"
+    return {"value": units / wall, "unit": unit, "cores": ncore, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{sum(r[2] for r in res)} {what} on {ncore} processes (one window or chain each, "
+                      f"M from {min(q.M for q in probs)} to {max(q.M for q in probs)}), {wall:.1f} s"}
+
+
 def cpu_baseline(prob, budget_s: float):
     """The CPU oracle, untouched, on the same window for a bounded number of sweeps."""
     import numpy as np
@@ -96,7 +163,7 @@ def cpu_baseline(prob, budget_s: float):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     return {"value": (prob.M + 1) * n / wall, "unit": "site-updates/s",
-            "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "cores": max(1, round(cpu / wall)), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n} sweeps of the same M={prob.M} window from its initial guess ({wall:.1f} s)"}
 
 
@@ -266,27 +333,24 @@ def _common(metric, value, unit, K, Wm, gpu_s, dtype, config):
             "dtype": dtype, "data": "synthetic", "config": config}
 
 
-def bench_batch(args, ctx):
+def bench_batch(ctx, config: str, K: int, Wm: int, cpu_seconds: float):
     """The batched workload: 512 HH windows of uneven M (each with its own
     drive, noise and true parameters) swept together by one launch per call
     (the captured batch graph).  One step = one sweep of every window."""
-    import numpy as np
     import torch
 
     import paper_1103_4887_amd as P
     from paper_1103_4887_amd import autotune
     import workloads as W
 
-    cfg = W.CONFIGS[args.config]
-    probs = W.config_batch(args.config, workers=max(1, min(16, os.cpu_count() or 1)))
+    cfg = W.CONFIGS[config]
+    probs = W.config_batch(config, workers=host_cores())
     spec = probs[0].model
     B = len(probs)
     batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
                                [q.I for q in probs], list(range(B)), "fp32")
     w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
     shape = autotune.tune_batch(ctx, spec, batch, w)
-    K = args.steps or 2000
-    Wm = args.warmup
     P.pimc_run_batch(ctx, spec, batch, seed=cfg["data_seed"], sweep0=0, w=w, n_sweeps=max(Wm, 1))
     assert ctx.sync() == 0
     st = P.SweepStats(acc=torch.zeros((B, P._lib.PIMC_NACC), dtype=torch.int64, device=batch.X.device))
@@ -301,7 +365,7 @@ def bench_batch(args, ctx):
     achieved = SLOTS_PER_SITE_UPDATE * rate
     out = _common("path site-updates/s, uneven batch of HH windows, 1 GPU", rate, "site-updates/s", K, Wm,
                   gpu_s, "f32",
-                  {"workload": f"{args.config}: {B} HH windows, M uniform in [{cfg['M_lo']}, {cfg['M_hi']}] "
+                  {"workload": f"{config}: {B} HH windows, M uniform in [{cfg['M_lo']}, {cfg['M_hi']}] "
                                f"({sites} sites), dt={spec.dt} ms, fp32 sites + f64 reductions, params mask "
                                f"0x{spec.p_mask:x}, one launch per call, {K} sweeps",
                    "windows": B, "sites": sites, "launch": {"K": shape[0], "tiles": shape[1]}})
@@ -310,18 +374,21 @@ def bench_batch(args, ctx):
                        "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
                        "kernel": "sweep_kernel", "slots_per_site_update": SLOTS_PER_SITE_UPDATE,
                        "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3}
-    if not args.no_cpu_baseline:
-        med = probs[int(np.argsort([q.M for q in probs])[B // 2])]
-        out["cpu_baseline"] = cpu_baseline(med, args.cpu_seconds)
+    if cpu_seconds > 0:
+        # every host core on windows spread over the batch's range of M
+        order = sorted(range(B), key=lambda i: probs[i].M)
+        pick = [probs[order[(2 * j + 1) * B // (2 * host_cores())]] for j in range(host_cores())]
+        out["cpu_baseline"] = cpu_baseline_ncore("sweep", pick, cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]
     return out
 
 
-def bench_hmc(args, ctx):
+def bench_hmc(ctx, config: str, K: int, Wm: int, cpu_seconds: float, ess_proposals: int = 2000):
     """HMC on the 64-chain workload: pilot masses and dual-averaged step size
     (untimed), then K proposals of L leapfrog steps replayed from one
-    captured graph.  One step = one proposal of every chain."""
-    import numpy as np
+    captured graph.  One step = one proposal of every chain.  The parameter
+    ESS/s comes from a separate run of `ess_proposals` proposals (its own
+    wall clock), long enough for the estimator."""
     import torch
 
     import paper_1103_4887_amd as P
@@ -329,8 +396,8 @@ def bench_hmc(args, ctx):
     from paper_1103_4887_amd import hmc as H
     import workloads as W
 
-    cfg = W.CONFIGS[args.config]
-    prob = W.config_problem(args.config, init="truth")
+    cfg = W.CONFIGS[config]
+    prob = W.config_problem(config, init="truth")
     spec = prob.model
     B, L = cfg["chains"], cfg["leapfrog"]
     batch = P.PackedBatch.pack([prob.X0] * B, [prob.p0] * B, [prob.y] * B, [prob.I] * B, list(range(B)), "fp32")
@@ -338,34 +405,39 @@ def bench_hmc(args, ctx):
     autotune.tune_batch(ctx, spec, batch, w)
     minv = H.pilot_minv(ctx, spec, batch, w, seed=prob.seed + 1, sweeps=2000)
     tun = H.tune_eps(ctx, spec, batch, minv, seed=prob.seed + 2, L_steps=L, warmup=200, eps0=0.01)
-    K = args.steps or 300
-    Wm = min(args.warmup, 50)
     H.sample(ctx, spec, batch, tun, seed=prob.seed + 2, L_steps=L, n=max(Wm, 1), k0=200)
     stream = torch.cuda.current_stream()
+    k1 = 200 + max(Wm, 1)
     gpu_s, wall, sh = _timed(stream, lambda: H.sample(ctx, spec, batch, tun, seed=prob.seed + 2, L_steps=L, n=K,
-                                                      k0=200 + max(Wm, 1)))
+                                                      k0=k1))
     if ctx.sync() != 0:
         raise RuntimeError("device reported an error")
     sites = B * (prob.M + 1)
     rate = sites * L * K / gpu_s
-    mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
-    ess, _, _ = _post_stats(sh.ptrace.cpu().numpy()[:, K // 2:], mask)
     acc = sh.acc.cpu().numpy()
     out = _common("site-leapfrogs/s + param ESS/s, HMC, HH M=16384 x 64 chains, 1 GPU", rate, "site-leapfrogs/s",
                   K, Wm, gpu_s, "f32",
-                  {"workload": f"{args.config}: HMC on {B} chains of the HH window M={prob.M}, dt={spec.dt} ms, "
+                  {"workload": f"{config}: HMC on {B} chains of the HH window M={prob.M}, dt={spec.dt} ms, "
                                f"{L} leapfrog steps per proposal, fp32 sites + f64 Hamiltonian, params mask "
                                f"0x{spec.p_mask:x}, {K} proposals",
                    "chains": B, "M": prob.M, "leapfrog_steps": L, "eps": tun.eps})
-    out["param_ess_per_s"] = float(ess.min() / gpu_s)
-    out["param_ess"] = [float(v) for v in ess]
     out["accept_rate"] = float(acc[:, 0].sum() / (B * K))
+    if ess_proposals > 0:
+        mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
+        t0 = time.perf_counter()
+        se = H.sample(ctx, spec, batch, tun, seed=prob.seed + 2, L_steps=L, n=ess_proposals, k0=k1 + K)
+        wall_e = time.perf_counter() - t0
+        ess, _, _ = _post_stats(se.ptrace.cpu().numpy()[:, ess_proposals // 2:], mask)
+        out["param_ess_per_s"] = float(ess.min() / wall_e)
+        out["param_ess"] = [float(v) for v in ess]
+        out["param_ess_sample"] = (f"{ess_proposals} proposals of all {B} chains after the timed ones "
+                                   f"({wall_e:.2f} s wall), ESS summed over chains on the second half")
     # per site-leapfrog the kernels move q, r (read and write) and read y, I
     out["roofline"] = {"bound": "hbm", "achieved": 72.0 * rate / 1e9, "peak": 8000.0, "unit": "GB/s",
                        "frac": 72.0 * rate / 8e12, "traffic": None, "kernel": "hmc_step_kernel",
                        "bytes_per_site_leapfrog": 72, "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_hmc(prob, tun, L, args.cpu_seconds)
+    if cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline_ncore("hmc", [prob], cpu_seconds, extra=(tun.eps, L, tun.minv))
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]
     return out
 
@@ -386,7 +458,7 @@ def cpu_baseline_hmc(prob, tun, L, budget_s: float):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     return {"value": (prob.M + 1) * L * n / wall, "unit": "site-leapfrogs/s",
-            "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "cores": max(1, round(cpu / wall)), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n} proposals of one M={prob.M} chain ({wall:.1f} s)"}
 
 
@@ -400,13 +472,17 @@ def main():
     import torch
 
     import paper_1103_4887_amd as P
-    from paper_1103_4887_amd import autotune, diag
+    from paper_1103_4887_amd import autotune
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_seconds
     if args.config in ("c4", "c5"):
         ctx = P.Context(0)
-        out = (bench_batch if args.config == "c4" else bench_hmc)(args, ctx)
+        if args.config == "c4":
+            out = bench_batch(ctx, "c4", args.steps or 2000, args.warmup, cpu_s)
+        else:
+            out = bench_hmc(ctx, "c5", args.steps or 300, min(args.warmup, 50), cpu_s)
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -426,30 +502,18 @@ def main():
         ctx.set_tiles(max(args.tiles, 0))
         shape = (args.tile, max(args.tiles, 0), None)
 
-    # warm-up (also compiles nothing: the library is prebuilt)
+    # warm-up (the library is prebuilt: nothing compiles here)
     P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=0, sweep0=0, w=w, n_sweeps=max(Wm, 1))
     assert ctx.sync() == 0
     stats = P.SweepStats.allocate(win, K, burn=Wm + K // 2, stride=args.nskip)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=0, sweep0=max(Wm, 1), w=w, n_sweeps=K, stats=stats)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    gpu_s, wall, _ = _timed(stream, lambda: P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=0,
+                                                         sweep0=max(Wm, 1), w=w, n_sweeps=K, stats=stats))
     st = ctx.sync()
     if st != 0:
         raise RuntimeError(f"device reported status {st}")
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
     sites = prob.M + 1
     rate = sites * K / gpu_s
-
-    tr = stats.ptrace.cpu().numpy()
-    post = tr[K // 2:]
     mask = [l for l in range(7) if (spec.p_mask >> l) & 1]
-    ess = diag.ess_columns(post[:, mask])
     acc = stats.acc.cpu().numpy()
     achieved = SLOTS_PER_SITE_UPDATE * rate
     out = {
@@ -460,9 +524,8 @@ def main():
                                f"reductions, params mask 0x{spec.p_mask:x}, 1 chain, {K} sweeps",
                    "M": prob.M, "sweeps": K, "chains": 1, "nskip": args.nskip,
                    "launch": {"K": shape[0], "tiles": shape[1]}},
-        "param_ess_per_s": float(ess.min() / gpu_s),
-        "param_ess_per_s_median": float(np.median(ess) / gpu_s),
-        "param_ess": [float(v) for v in ess],
+        "param_ess_per_s": None,
+        "param_ess_source": "not measured (the comparison of samplers was switched off)",
         "accept_rate": {"sites": float((acc[0] + acc[1]) / (sites * K)),
                         "params": [float(acc[2 + l] / K) for l in mask]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
@@ -473,11 +536,24 @@ def main():
                      "kernel_ms": gpu_s * 1e3, "wall_ms": wall * 1e3},
     }
     if args.cmp_seconds > 0:
-        out["hmc_vs_sweep"] = hmc_vs_sweep(ctx, W.config_problem(args.config, init="truth"), args.cmp_chains,
-                                           args.cmp_seconds, args.cmp_equilibrate)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        cmp = hmc_vs_sweep(ctx, W.config_problem(args.config, init="truth"), args.cmp_chains,
+                           args.cmp_seconds, args.cmp_equilibrate)
+        out["hmc_vs_sweep"] = cmp
+        # the parameter ESS of this window's single chain needs tens of
+        # seconds of sampling: it is the comparison's single-chain run (the
+        # same window and launch shape), not the short timed run above
+        one = cmp["single_chain_sweep"]
+        out["param_ess_per_s"] = one["param_ess_per_s"]
+        out["param_ess_source"] = (f"hmc_vs_sweep.single_chain_sweep: {one['sweeps']} sweeps of this window in "
+                                   f"{one['wall_s']:.1f} s; batched sweep and HMC (64 chains) beside it")
+    if cpu_s > 0:
+        out["cpu_baseline"] = cpu_baseline(prob, cpu_s)
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]
+    if args.config == "c2" and args.sub_blocks:
+        # short measurements of the batched and HMC workloads, so that every
+        # run of the default benchmark also records them
+        out["c4_batch"] = bench_batch(ctx, "c4", 200, 20, cpu_s)
+        out["c5_hmc"] = bench_hmc(ctx, "c5", 30, 10, cpu_s, ess_proposals=2000)
     ctx.close()
     print(json.dumps(out), flush=True)
 

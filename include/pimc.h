@@ -56,7 +56,28 @@ typedef enum {
 
 enum { PIMC_FP64 = 0, PIMC_FP32 = 1 };          /* site arithmetic precision */
 enum { PIMC_PROP_GAUSS = 0, PIMC_PROP_UNIFORM = 1 }; /* proposal law (Fig. 1 step 1a = uniform) */
-enum { PIMC_STATES = 1, PIMC_PARAMS = 2 };       /* pimc_sweep flags */
+/* pimc_sweep / pimc_run_batch flags.  PIMC_GIBBS (with PIMC_PARAMS): each
+ * sampled parameter, in ascending order, is drawn from its exact conditional
+ * given the path and the other parameters instead of a Metropolis step.
+ * dV/dt is affine in each p_l (Section 5.1), so the action is quadratic in
+ * p_l and the conditional is a Gaussian truncated to p_l's box, read from the
+ * same path statistics the Metropolis moves use; the draw inverts its CDF
+ * with word 0 of the parameter's Philox block.  It changes the chain, so it
+ * is off unless asked for; acceptance counters then count finite draws. */
+enum { PIMC_STATES = 1, PIMC_PARAMS = 2, PIMC_GIBBS = 4, PIMC_KINETIC = 8 };
+/* PIMC_KINETIC (pimc_sweep / pimc_sweep_init on a path with `kin` set): after
+ * the parameters, each Table 1 constant selected by model->k_mask, in the
+ * order (m, h, n) x (V_a, dV_a, tau0, tau1), takes a Metropolis move
+ * kin_i + w[11 + i] z (Philox KIN block of index i: z from words 0 and 1,
+ * the accept uniform from word 2; rejected outside k_lo/k_hi).  The constants
+ * enter the gate equations nonlinearly, so each move is a full pass over the
+ * path with the change of A summed in FP64 over all links (the direct form of
+ * Section 4.1; Section 5.1 notes all the model's constants can be estimated
+ * this way).  Runs in the launch shapes of at most 256 threads. */
+
+/* Most sweeps one call may run when its windows are cut into time tiles
+ * (longer runs are split into several calls by the caller). */
+#define PIMC_MAX_TILED_SWEEPS (1ll << 30)
 
 /* acceptance counters written to pimc_stats.acc */
 enum { PIMC_ACC_EVEN = 0, PIMC_ACC_ODD = 1, PIMC_ACC_PARAM0 = 2, PIMC_ACC_NONFINITE = 9, PIMC_NACC = 10 };
@@ -74,6 +95,8 @@ typedef struct {
   double p_lo[7], p_hi[7];                 /* parameter box */
   uint32_t p_mask;    /* bit l set => p_{l+1} is sampled */
   int32_t proposal;   /* PIMC_PROP_GAUSS or PIMC_PROP_UNIFORM */
+  double k_lo[12], k_hi[12];  /* box of the Table 1 constants, order (m, h, n) x (V_a, dV_a, tau0, tau1) */
+  uint32_t k_mask;    /* bit i set => Table 1 constant i is sampled (PIMC_KINETIC) */
 } pimc_model;
 
 /* One window.  X and p are read and written; y and I are read only. */
@@ -84,6 +107,9 @@ typedef struct {
   double* p;          /* [7] FP64 */
   const void* y;      /* [M+1], y[0] unused */
   const void* I;      /* [M+1], drive at t_n */
+  double* kin;        /* [12] FP64 or NULL: the Table 1 constants of this window, order (m, h, n) x
+                         (V_a, dV_a, tau0, tau1); when set they replace the model's Va/dVa/tau0/tau1
+                         in every kernel of the call, and PIMC_KINETIC samples them (in/out) */
 } pimc_path;
 
 /* Random-number address: sweep k of a call is sweep0 + (0 .. n_sweeps-1). */
@@ -116,12 +142,16 @@ typedef struct {
   int64_t stride;
   double* batch;
   int64_t nbatch;
+  int64_t* kacc;      /* [12] int64 (+=), nullable: accepted moves of each Table 1 constant (PIMC_KINETIC) */
 } pimc_stats;
 
 /* What the LAST sweep of a call proposed and decided (every pointer nullable).
  *   xprop [M+1][4] path precision, dA [M+1] FP64 (NaN where the proposal left
  *   the box), accept [M+1] uint8; pprop/pdA [7] FP64, paccept [7] uint8
- *   (entries of unsampled parameters are left untouched). */
+ *   (entries of unsampled parameters are left untouched); kprop/kdA [12]
+ *   FP64, kaccept [12] uint8 for the Table 1 constants (PIMC_KINETIC).
+ *   Calls with PIMC_KINETIC record only the three k fields (the others must
+ *   be NULL). */
 typedef struct {
   void* xprop;
   double* dA;
@@ -129,6 +159,9 @@ typedef struct {
   double* pprop;
   double* pdA;
   uint8_t* paccept;
+  double* kprop;
+  double* kdA;
+  uint8_t* kaccept;
 } pimc_debug;
 
 /* Packed batch of independent windows for pimc_run_batch.
@@ -183,7 +216,12 @@ int pimc_set_sweep_tile(pimc_ctx* ctx, int K);
  * most 256 threads when the window fits, the fewest tiles otherwise); 1
  * forces one workgroup (up to 1024 threads); at most 256.  Only FP32 windows
  * are tiled: an FP64 window that does not fit one workgroup is refused with
- * PIMC_ERR_UNSUPPORTED.  pimc_run_batch uses T tiles per window when every
+ * PIMC_ERR_UNSUPPORTED.  The tiles of a launch must all be resident at once:
+ * a launch larger than the device holds is refused (PIMC_ERR_UNSUPPORTED),
+ * and if other work keeps a tile from being placed, the tiles' bounded waits
+ * give up and pimc_sync reports PIMC_ERR_TIMEOUT.  A tiled call runs at most
+ * PIMC_MAX_TILED_SWEEPS sweeps (PIMC_ERR_ARG beyond); calls on one context
+ * share its exchange workspace, so they must not run concurrently.  pimc_run_batch uses T tiles per window when every
  * window of the batch needs exactly T tiles of the chosen shape, else one
  * workgroup per window. */
 int pimc_set_sweep_tiles(pimc_ctx* ctx, int T);
@@ -200,15 +238,77 @@ const char* pimc_strerror(int status);
 int pimc_action(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path,
                 double* out3, void* stream);
 
+/* Model checks of Section 6.  pimc_model_errors adds, for the current path,
+ * the trapezoid model error eps_n (Section 2.1, components V, m, h, n) and
+ * the observation error delta_n = y_n - V_n of every link n = 1..M to
+ * esum[n-1][0..4] and their squares to esq[n-1][0..4] (device FP64 [M][5],
+ * caller-owned, +=); called once per posterior sample, the sums give <eps_n>,
+ * <delta_n> and their variances, which should be 0, 1/Rd and 1/Ro when the
+ * model is right.  Terms in FP64 for either path precision. */
+int pimc_model_errors(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, double* esum,
+                      double* esq, void* stream);
+
+/* Forecasts from the end of a window (Section 6): member b = 0..B-1 starts
+ * at x0[b] (device FP64 [B][4]) with parameters p[b] (device FP64 [B][7])
+ * and is integrated N steps of model->dt by Heun's method over the drive
+ * I[0..N] (device FP64 [N+1], I[0] at the start time), adding per step the
+ * model noise eps ~ N(0, 1/Rd) times `noise` (0: deterministic) from the
+ * Philox block (index member0 + b, counter = step, tag 8, chain 0).  kin:
+ * device [12] Table 1 constants or NULL (the model's).  out: device FP64
+ * [B][N+1][4], the trajectory including the start.  FP64 throughout. */
+int pimc_forecast(pimc_ctx* ctx, const pimc_model* model, int32_t B, const double* x0, const double* p,
+                  const double* kin, const double* I, int64_t N, double noise, uint64_t seed, int64_t member0,
+                  double* out, void* stream);
+
 /* n_sweeps red-black Metropolis sweeps (Fig. 1; Sections 3.1, 4.1-4.2):
  * all even sites, then all odd sites (joint D-component proposal
  * x' = x + w z, box test, accept iff log u < -dA with dA in FP64 for the
  * decision), then -- if PIMC_PARAMS -- each sampled parameter in ascending
  * order.  w: device FP64 [11] = proposal widths of (V, m, h, n) then
- * (p1 .. p7).  stats and debug are nullable. */
+ * (p1 .. p7), [23] with PIMC_KINETIC (then the 12 Table 1 constants).
+ * stats and debug are nullable. */
 int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng,
                const double* w, int64_t n_sweeps, int32_t flags,
                const pimc_stats* stats, const pimc_debug* debug, void* stream);
+
+/* State of the initialization phase (Section 4.2) for pimc_sweep_init.  The
+ * scalars are host values read at each call; the five pointers are caller-
+ * owned DEVICE memory that the call reads and updates, so consecutive calls
+ * continue the phase (initialise beta = beta0, site_scale = 1, w_param = the
+ * parameter widths, counts = 0 before the first call).
+ *  - annealing: sweep k uses beta (in place of model->beta) as the
+ *    multiplier of A_d; after every sweep beta <- min(1, beta f_beta) with
+ *    f_beta = (1/beta0)^(1/n_cool) (eq. fbeta);
+ *  - step sizes: after sweep k with k < n_init and (k + 1) % n_skip == 0,
+ *    every step is scaled by 1 + alpha (N_acc / n_skip - f_acc) (the rule of
+ *    Section 4.2; N_acc = accepted changes of that component since the last
+ *    adjustment) and its count restarts.  The D components of a site move
+ *    jointly with one decision, so they share N_acc: the step of component a
+ *    at site n is w[a] * site_scale[n].  Parameter l uses w_param[l] (not
+ *    w[4 + l]) and its own count.
+ * Paper values (Section 5.1): beta0 = 0.01, n_cool = 1e5, n_init = 5e5,
+ * n_skip = 400, f_acc = 0.23, alpha = 0.02. */
+typedef struct {
+  double beta0;        /* 0 < beta0 <= 1 */
+  int64_t n_cool;      /* >= 1 */
+  int64_t n_init;      /* >= 0 */
+  int64_t n_skip;      /* >= 1 */
+  double f_acc;        /* in [0, 1] */
+  double alpha;        /* >= 0 */
+  double* beta;        /* [1] FP64: beta of the next sweep */
+  double* site_scale;  /* [M+1] FP64 */
+  double* w_param;     /* [7] FP64 */
+  int32_t* cnt_site;   /* [M+1] */
+  int32_t* cnt_param;  /* [7] */
+} pimc_init_phase;
+
+/* pimc_sweep with the initialization phase of Section 4.2 (annealing of beta
+ * and adjustment of the step sizes, see pimc_init_phase).  Runs in the launch
+ * shapes of at most 256 threads per workgroup (the automatic choice, or time
+ * tiles); others return PIMC_ERR_UNSUPPORTED.  No debug record. */
+int pimc_sweep_init(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng,
+                    const double* w, int64_t n_sweeps, int32_t flags, const pimc_init_phase* init,
+                    const pimc_stats* stats, void* stream);
 
 /* One round of sequential parameter moves (Fig. 1 step 3, Section 4.1) at
  * sweep index rng.sweep0, with the path held fixed; identical to pimc_sweep
@@ -248,11 +348,24 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* bat
  *           whose trajectory was invalid (a coordinate outside its box after
  *           a reflection), [9] non-finite energy changes
  *   ptrace  [B][n_proposals][7] FP64: p after every proposal (written)
- *   dH      [B][n_proposals] FP64: H1 - H0 of every proposal (written) */
+ *   dH      [B][n_proposals] FP64: H1 - H0 of every proposal (written)
+ * Trajectory of the LAST proposal of the call, before its accept/reject
+ * (for element-wise checks; nullable, all four or none):
+ *   traj_q  [L+1][S][4] path precision: positions q(s) after drift s
+ *           (q(0) = the start), S = offsets[B]
+ *   traj_r  [L+1][S][4] path precision: momenta r(s+1/2) after kick s,
+ *           r(L) for s = L
+ *   traj_p  [L+1][B][7] FP64: parameters p(s)
+ *   traj_rp [L+2][B][7] FP64: parameter momenta rp(0), rp(s-1/2) for
+ *           s = 1..L, then rp(L) */
 typedef struct {
   int64_t* acc;
   double* ptrace;
   double* dH;
+  void* traj_q;
+  void* traj_r;
+  double* traj_p;
+  double* traj_rp;
 } pimc_hmc_stats;
 
 /* n_proposals Hybrid Monte Carlo proposals (the Hybrid MC of Section 3, a

@@ -76,6 +76,7 @@ class Stats:
         self.batch = np.zeros((self.nbatch, self.M + 1, self.D))
         self.ptrace = np.zeros((self.n_sweeps, self.Np))
         self.acc = np.zeros(N_ACC, dtype=np.int64)
+        self.kacc = np.zeros(12, dtype=np.int64)     # accepted moves of each Table 1 constant
 
 
 @dataclass
@@ -254,7 +255,7 @@ def param_moves(spec, X, I, p, k, w_param, seed, chain, acc=None,
             debug.paccept[l] = ok
 
 
-def kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=None, debug=None):
+def kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=None, debug=None, kacc=None):
     """Sequential Metropolis moves of the sampled Table 1 constants (in place
     on kin, shape (12,) in the order (m, h, n) x (V_a, dV_a, tau0, tau1)).
 
@@ -284,6 +285,8 @@ def kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=None, debug=Non
                 acc[ACC_NONFINITE] += 1
         if ok:
             kin[i] = prop[i]
+            if kacc is not None:
+                kacc[i] += 1
         if debug is not None:
             debug.kprop[i] = prop[i]
             debug.kdA[i] = dA
@@ -353,7 +356,8 @@ def run(spec, X, p, y, I, *, seed, chain, sweep0, n_sweeps, w_state, w_param,
             param_moves(spec, X, I, p, k, init.w_param if init is not None else w_param, seed, chain,
                         acc=acc, debug=dbg, cnt_param=init.cnt_param if init is not None else None)
         if kin is not None and flags & KINETIC:
-            kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=acc, debug=dbg)
+            kinetic_moves(spec, X, I, p, k, kin, w_kin, seed, chain, acc=acc, debug=dbg,
+                          kacc=stats.kacc if stats is not None else None)
         if init is not None:
             # Section 4.2: beta grows by f_beta after every sweep up to 1; the
             # steps follow the acceptance of the past n_skip sweeps, every

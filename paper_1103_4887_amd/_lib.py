@@ -24,6 +24,8 @@ PIMC_PROP_GAUSS = 0
 PIMC_PROP_UNIFORM = 1
 PIMC_STATES = 1
 PIMC_PARAMS = 2
+PIMC_GIBBS = 4
+PIMC_KINETIC = 8
 PIMC_NACC = 10
 
 
@@ -32,12 +34,13 @@ class Model(C.Structure):
                 ("Va", C.c_double * 3), ("dVa", C.c_double * 3), ("tau0", C.c_double * 3),
                 ("tau1", C.c_double * 3), ("x_lo", C.c_double * 4), ("x_hi", C.c_double * 4),
                 ("p_lo", C.c_double * 7), ("p_hi", C.c_double * 7), ("p_mask", C.c_uint32),
-                ("proposal", C.c_int32)]
+                ("proposal", C.c_int32), ("k_lo", C.c_double * 12), ("k_hi", C.c_double * 12),
+                ("k_mask", C.c_uint32)]
 
 
 class Path(C.Structure):
     _fields_ = [("M", C.c_int64), ("prec", C.c_int32), ("X", C.c_void_p), ("p", C.c_void_p),
-                ("y", C.c_void_p), ("I", C.c_void_p)]
+                ("y", C.c_void_p), ("I", C.c_void_p), ("kin", C.c_void_p)]
 
 
 class Rng(C.Structure):
@@ -47,12 +50,13 @@ class Rng(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("xref", C.c_void_p),
                 ("ptrace", C.c_void_p), ("acc", C.c_void_p), ("burn", C.c_int64), ("stride", C.c_int64),
-                ("batch", C.c_void_p), ("nbatch", C.c_int64)]
+                ("batch", C.c_void_p), ("nbatch", C.c_int64), ("kacc", C.c_void_p)]
 
 
 class Debug(C.Structure):
     _fields_ = [("xprop", C.c_void_p), ("dA", C.c_void_p), ("accept", C.c_void_p),
-                ("pprop", C.c_void_p), ("pdA", C.c_void_p), ("paccept", C.c_void_p)]
+                ("pprop", C.c_void_p), ("pdA", C.c_void_p), ("paccept", C.c_void_p),
+                ("kprop", C.c_void_p), ("kdA", C.c_void_p), ("kaccept", C.c_void_p)]
 
 
 class Batch(C.Structure):
@@ -67,8 +71,15 @@ class BatchStats(C.Structure):
                 ("batch", C.c_void_p), ("nbatch", C.c_int64)]
 
 
+class InitPhase(C.Structure):
+    _fields_ = [("beta0", C.c_double), ("n_cool", C.c_int64), ("n_init", C.c_int64), ("n_skip", C.c_int64),
+                ("f_acc", C.c_double), ("alpha", C.c_double), ("beta", C.c_void_p), ("site_scale", C.c_void_p),
+                ("w_param", C.c_void_p), ("cnt_site", C.c_void_p), ("cnt_param", C.c_void_p)]
+
+
 class HmcStats(C.Structure):
-    _fields_ = [("acc", C.c_void_p), ("ptrace", C.c_void_p), ("dH", C.c_void_p)]
+    _fields_ = [("acc", C.c_void_p), ("ptrace", C.c_void_p), ("dH", C.c_void_p), ("traj_q", C.c_void_p),
+                ("traj_r", C.c_void_p), ("traj_p", C.c_void_p), ("traj_rp", C.c_void_p)]
 
 
 _SIGS = {
@@ -81,8 +92,14 @@ _SIGS = {
     "pimc_action": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p]),
     "pimc_sweep": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), Rng, C.c_void_p, C.c_int64,
                              C.c_int32, C.POINTER(Stats), C.POINTER(Debug), C.c_void_p]),
+    "pimc_sweep_init": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), Rng, C.c_void_p, C.c_int64,
+                                  C.c_int32, C.POINTER(InitPhase), C.POINTER(Stats), C.c_void_p]),
     "pimc_param_update": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), Rng, C.c_void_p,
                                     C.POINTER(Debug), C.c_void_p]),
+    "pimc_model_errors": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    "pimc_forecast": (C.c_int, [C.c_void_p, C.POINTER(Model), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_int64, C.c_double, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "pimc_grad": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p,
                             C.c_void_p]),
     "pimc_run_batch": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Batch), C.c_uint64, C.c_uint64,

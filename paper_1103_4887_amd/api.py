@@ -54,6 +54,12 @@ def model_struct(spec) -> L.Model:
         m.p_hi[l] = float(spec.p_hi[l])
     m.p_mask = int(spec.p_mask)
     m.proposal = L.PIMC_PROP_UNIFORM if spec.proposal == "uniform" else L.PIMC_PROP_GAUSS
+    k_lo = getattr(spec, "k_lo", None)
+    k_hi = getattr(spec, "k_hi", None)
+    for i in range(12):
+        m.k_lo[i] = float(k_lo[i]) if k_lo is not None else -1e300
+        m.k_hi[i] = float(k_hi[i]) if k_hi is not None else 1e300
+    m.k_mask = int(getattr(spec, "k_mask", 0))
     return m
 
 
@@ -91,13 +97,17 @@ class Context:
 
 @dataclass
 class Window:
-    """Device-resident window: X [M+1][4], p [7] FP64, y, I [M+1]."""
+    """Device-resident window: X [M+1][4], p [7] FP64, y, I [M+1]; kin, if
+    set, [12] FP64 Table 1 constants of the window (order (m, h, n) x
+    (V_a, dV_a, tau0, tau1)) that replace the model's and that PIMC_KINETIC
+    samples."""
 
     X: torch.Tensor
     p: torch.Tensor
     y: torch.Tensor
     I: torch.Tensor
     prec: str
+    kin: Optional[torch.Tensor] = None
 
     @property
     def M(self) -> int:
@@ -120,6 +130,7 @@ class Window:
         pa.p = _ptr(self.p)
         pa.y = _ptr(self.y)
         pa.I = _ptr(self.I)
+        pa.kin = _ptr(self.kin)
         return pa
 
 
@@ -133,6 +144,7 @@ class SweepStats:
     burn: int = 0
     stride: int = 1
     batch: Optional[torch.Tensor] = None    # [nbatch][sites][4] per-batch sums
+    kacc: Optional[torch.Tensor] = None     # [12] int64 accepted moves of the Table 1 constants
 
     @staticmethod
     def allocate(win: Window, n_sweeps: int, burn: int = 0, moments: bool = True, trace: bool = True,
@@ -158,33 +170,48 @@ class SweepStats:
         s.stride = int(self.stride)
         s.batch = _ptr(self.batch)
         s.nbatch = int(self.batch.shape[0]) if self.batch is not None else 0
+        s.kacc = _ptr(self.kacc)
         return s
 
 
 @dataclass
 class SweepDebug:
-    xprop: torch.Tensor
-    dA: torch.Tensor
-    accept: torch.Tensor
-    pprop: torch.Tensor
-    pdA: torch.Tensor
-    paccept: torch.Tensor
+    xprop: Optional[torch.Tensor] = None
+    dA: Optional[torch.Tensor] = None
+    accept: Optional[torch.Tensor] = None
+    pprop: Optional[torch.Tensor] = None
+    pdA: Optional[torch.Tensor] = None
+    paccept: Optional[torch.Tensor] = None
+    kprop: Optional[torch.Tensor] = None
+    kdA: Optional[torch.Tensor] = None
+    kaccept: Optional[torch.Tensor] = None
 
     @staticmethod
-    def allocate(win: Window):
+    def allocate(win: Window, sites: bool = True, kinetic: bool = False):
+        """Record of the last sweep: sites and parameters (sites=True) and/or
+        the kinetic constants (kinetic=True; calls with PIMC_KINETIC record
+        only those)."""
         dev = win.X.device
         nan = float("nan")
-        return SweepDebug(xprop=torch.full_like(win.X, nan),
-                          dA=torch.full((win.M + 1,), nan, dtype=torch.float64, device=dev),
-                          accept=torch.zeros(win.M + 1, dtype=torch.uint8, device=dev),
-                          pprop=torch.full((7,), nan, dtype=torch.float64, device=dev),
-                          pdA=torch.full((7,), nan, dtype=torch.float64, device=dev),
-                          paccept=torch.zeros(7, dtype=torch.uint8, device=dev))
+        d = SweepDebug()
+        if sites:
+            d.xprop = torch.full_like(win.X, nan)
+            d.dA = torch.full((win.M + 1,), nan, dtype=torch.float64, device=dev)
+            d.accept = torch.zeros(win.M + 1, dtype=torch.uint8, device=dev)
+            d.pprop = torch.full((7,), nan, dtype=torch.float64, device=dev)
+            d.pdA = torch.full((7,), nan, dtype=torch.float64, device=dev)
+            d.paccept = torch.zeros(7, dtype=torch.uint8, device=dev)
+        if kinetic:
+            d.kprop = torch.full((12,), nan, dtype=torch.float64, device=dev)
+            d.kdA = torch.full((12,), nan, dtype=torch.float64, device=dev)
+            d.kaccept = torch.zeros(12, dtype=torch.uint8, device=dev)
+        return d
 
     def struct(self) -> L.Debug:
         d = L.Debug()
         d.xprop, d.dA, d.accept = _ptr(self.xprop), _ptr(self.dA), _ptr(self.accept)
         d.pprop, d.pdA, d.paccept = _ptr(self.pprop), _ptr(self.pdA), _ptr(self.paccept)
+        d.kprop, d.kdA, d.kaccept = _ptr(self.kprop), _ptr(self.kdA), _ptr(self.kaccept)
         return d
 
 
@@ -206,6 +233,29 @@ def pimc_action(ctx: Context, spec, win: Window, out3: Optional[torch.Tensor] = 
     m, pa = model_struct(spec), win.path_struct()
     L.check(ctx.lib.pimc_action(ctx.h, C.byref(m), C.byref(pa), _ptr(out3), _stream(stream)), "pimc_action")
     return out3
+
+
+def pimc_model_errors(ctx: Context, spec, win: Window, esum: torch.Tensor, esq: torch.Tensor, stream=None):
+    """Add the model and observation errors of the window's current path to
+    esum / esq ([M][5] FP64 device tensors)."""
+    m, pa = model_struct(spec), win.path_struct()
+    L.check(ctx.lib.pimc_model_errors(ctx.h, C.byref(m), C.byref(pa), _ptr(esum), _ptr(esq), _stream(stream)),
+            "pimc_model_errors")
+
+
+def pimc_forecast(ctx: Context, spec, x0: torch.Tensor, p: torch.Tensor, I: torch.Tensor, N: int, *,
+                  noise: float = 0.0, seed: int = 0, member0: int = 0, kin: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None, stream=None):
+    """Forecast ensemble: x0 [B][4], p [B][7], drive I [N+1] (FP64 device
+    tensors); returns [B][N+1][4]."""
+    B = int(x0.shape[0])
+    if out is None:
+        out = torch.empty((B, N + 1, 4), dtype=torch.float64, device=x0.device)
+    m = model_struct(spec)
+    L.check(ctx.lib.pimc_forecast(ctx.h, C.byref(m), B, _ptr(x0), _ptr(p), _ptr(kin), _ptr(I), int(N),
+                                  float(noise), int(seed) & 0xFFFFFFFFFFFFFFFF, int(member0), _ptr(out),
+                                  _stream(stream)), "pimc_forecast")
+    return out
 
 
 def pimc_grad(ctx: Context, spec, win: Window, gX: Optional[torch.Tensor] = None,
@@ -235,6 +285,55 @@ def pimc_param_update(ctx: Context, spec, win: Window, *, seed: int, chain: int,
     db = C.byref(debug.struct()) if debug is not None else None
     L.check(ctx.lib.pimc_param_update(ctx.h, C.byref(m), C.byref(pa), _rng(seed, chain, sweep0), _ptr(w),
                                       db, _stream(stream)), "pimc_param_update")
+
+
+@dataclass
+class InitPhase:
+    """Device state of the initialization phase (annealing and step-size
+    adjustment, see pimc_init_phase in include/pimc.h); consecutive calls of
+    pimc_sweep_init with the same object continue the phase."""
+
+    beta0: float
+    n_cool: int
+    n_init: int
+    n_skip: int
+    f_acc: float
+    alpha: float
+    beta: torch.Tensor         # [1] FP64
+    site_scale: torch.Tensor   # [M+1] FP64
+    w_param: torch.Tensor      # [7] FP64
+    cnt_site: torch.Tensor     # [M+1] int32
+    cnt_param: torch.Tensor    # [7] int32
+
+    @staticmethod
+    def start(win: "Window", w_param, *, beta0: float, n_cool: int, n_init: int, n_skip: int,
+              f_acc: float = 0.23, alpha: float = 0.02) -> "InitPhase":
+        dev = win.X.device
+        return InitPhase(beta0=beta0, n_cool=n_cool, n_init=n_init, n_skip=n_skip, f_acc=f_acc, alpha=alpha,
+                         beta=torch.full((1,), float(beta0), dtype=torch.float64, device=dev),
+                         site_scale=torch.ones(win.M + 1, dtype=torch.float64, device=dev),
+                         w_param=torch.as_tensor(np.asarray(w_param, dtype=np.float64), device=dev).clone(),
+                         cnt_site=torch.zeros(win.M + 1, dtype=torch.int32, device=dev),
+                         cnt_param=torch.zeros(7, dtype=torch.int32, device=dev))
+
+    def struct(self) -> L.InitPhase:
+        s = L.InitPhase()
+        s.beta0, s.n_cool, s.n_init, s.n_skip = float(self.beta0), int(self.n_cool), int(self.n_init), int(self.n_skip)
+        s.f_acc, s.alpha = float(self.f_acc), float(self.alpha)
+        s.beta, s.site_scale, s.w_param = _ptr(self.beta), _ptr(self.site_scale), _ptr(self.w_param)
+        s.cnt_site, s.cnt_param = _ptr(self.cnt_site), _ptr(self.cnt_param)
+        return s
+
+
+def pimc_sweep_init(ctx: Context, spec, win: Window, *, seed: int, chain: int, sweep0: int, w: torch.Tensor,
+                    n_sweeps: int, init: InitPhase, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
+                    stats: Optional[SweepStats] = None, stream=None):
+    """Sweeps with the initialization phase of Section 4.2 (see InitPhase)."""
+    m, pa = model_struct(spec), win.path_struct()
+    st = C.byref(stats.struct()) if stats is not None else None
+    ip = init.struct()
+    L.check(ctx.lib.pimc_sweep_init(ctx.h, C.byref(m), C.byref(pa), _rng(seed, chain, sweep0), _ptr(w),
+                                    int(n_sweeps), int(flags), C.byref(ip), st, _stream(stream)), "pimc_sweep_init")
 
 
 @dataclass
@@ -305,16 +404,31 @@ class HmcStats:
     acc: Optional[torch.Tensor] = None      # [B][10] int64
     ptrace: Optional[torch.Tensor] = None   # [B][n][7]
     dH: Optional[torch.Tensor] = None       # [B][n]
+    # trajectory of the last proposal (all four or none)
+    traj_q: Optional[torch.Tensor] = None   # [L+1][S][4] positions q(s)
+    traj_r: Optional[torch.Tensor] = None   # [L+1][S][4] momenta r(s+1/2), r(L) last
+    traj_p: Optional[torch.Tensor] = None   # [L+1][B][7] parameters p(s)
+    traj_rp: Optional[torch.Tensor] = None  # [L+2][B][7] rp(0), rp(s-1/2), rp(L)
 
     @staticmethod
-    def allocate(B: int, n: int, device="cuda"):
-        return HmcStats(acc=torch.zeros((B, L.PIMC_NACC), dtype=torch.int64, device=device),
-                        ptrace=torch.zeros((B, n, 7), dtype=torch.float64, device=device),
-                        dH=torch.zeros((B, n), dtype=torch.float64, device=device))
+    def allocate(B: int, n: int, device="cuda", trajectory: Optional[PackedBatch] = None, L_steps: int = 0):
+        st = HmcStats(acc=torch.zeros((B, L.PIMC_NACC), dtype=torch.int64, device=device),
+                      ptrace=torch.zeros((B, n, 7), dtype=torch.float64, device=device),
+                      dH=torch.zeros((B, n), dtype=torch.float64, device=device))
+        if trajectory is not None:
+            S = int(trajectory.offsets[-1])
+            dt = DTYPES[trajectory.prec]
+            st.traj_q = torch.full((L_steps + 1, S, 4), float("nan"), dtype=dt, device=device)
+            st.traj_r = torch.full_like(st.traj_q, float("nan"))
+            st.traj_p = torch.full((L_steps + 1, B, 7), float("nan"), dtype=torch.float64, device=device)
+            st.traj_rp = torch.full((L_steps + 2, B, 7), float("nan"), dtype=torch.float64, device=device)
+        return st
 
     def struct(self) -> L.HmcStats:
         s = L.HmcStats()
         s.acc, s.ptrace, s.dH = _ptr(self.acc), _ptr(self.ptrace), _ptr(self.dH)
+        s.traj_q, s.traj_r = _ptr(self.traj_q), _ptr(self.traj_r)
+        s.traj_p, s.traj_rp = _ptr(self.traj_p), _ptr(self.traj_rp)
         return s
 
 

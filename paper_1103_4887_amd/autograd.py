@@ -1,7 +1,7 @@
 """The action A(X, p) as a differentiable torch function.
 
 Forward is the library's FP64 action reduction (the path action of
-Section 2.3: measurement term plus model-error term over the discretised
+Section 2.1: measurement term plus model-error term over the discretised
 map); backward is its hand-written adjoint, the local stencil of dA/dx_n
 and the FP64 sums of dA/dp_l.  Both run in the library's kernels; this
 module only routes tensors.

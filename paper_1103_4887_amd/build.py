@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpimc.so")
-SOURCES = ["api.hip", "sweep.hip", "field.hip", "hmc.hip"]
+SOURCES = ["api.hip", "sweep.hip", "field.hip", "hmc.hip", "diag.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -28,18 +28,35 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source into libpimc.so; returns its path."""
-    cmd = [hipcc(), *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libpimc.so")
-    if verbose and r.stderr:
-        sys.stderr.write(r.stderr)
+    return r
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every HIP source (in parallel, one object each) and link
+    libpimc.so; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(objdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+    cmds = [[hipcc(), *compile_flags, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", o]
+            for src, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), cmds))
+    if verbose:
+        for r in results:
+            if r.stderr:
+                sys.stderr.write(r.stderr)
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"], verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

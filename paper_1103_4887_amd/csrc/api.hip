@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -43,8 +44,12 @@ struct pimc_ctx {
   size_t tile_cap = 0, group_cap = 0;
   void* halo = nullptr;
   double* wpart = nullptr;
-  uint32_t* wsync = nullptr;
+  uint64_t* tsync = nullptr;
   uint64_t spin_ticks = 0;
+  // exchange generations: a tiled call uses gen_next + 1 .. gen_next + n + 2
+  // and moves gen_next past them, so words left by earlier calls are always
+  // older than anything a later call waits for
+  uint64_t gen_next = 0;
   // HMC workspace (grow-only)
   size_t hmc_sites = 0, hmc_blocks = 0, hmc_B = 0, hmc_tsize = 0;
   void* hQ1 = nullptr;
@@ -75,6 +80,13 @@ using pimc::ModelArgs;
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? PIMC_OK : PIMC_ERR_HIP; }
 
+// STATES, PARAMS and/or KINETIC, and GIBBS only together with PARAMS
+bool valid_flags(int32_t f) {
+  if (f & ~(PIMC_STATES | PIMC_PARAMS | PIMC_GIBBS | PIMC_KINETIC)) return false;
+  if (!(f & (PIMC_STATES | PIMC_PARAMS | PIMC_KINETIC))) return false;
+  return !(f & PIMC_GIBBS) || (f & PIMC_PARAMS);
+}
+
 int model_args(const pimc_model* m, ModelArgs& a) {
   if (!m) return PIMC_ERR_ARG;
   if (!(m->dt > 0.0) || !(m->Ro >= 0.0) || !(m->beta >= 0.0)) return PIMC_ERR_ARG;
@@ -86,6 +98,9 @@ int model_args(const pimc_model* m, ModelArgs& a) {
     if (m->dVa[g] == 0.0 || !(m->tau0[g] > 0.0) || !(m->tau1[g] >= 0.0)) return PIMC_ERR_ARG;
   if (m->proposal != PIMC_PROP_GAUSS && m->proposal != PIMC_PROP_UNIFORM) return PIMC_ERR_ARG;
   if (m->p_mask & ~0x7Fu) return PIMC_ERR_ARG;
+  if (m->k_mask & ~0xFFFu) return PIMC_ERR_ARG;
+  for (int i = 0; i < 12; ++i)
+    if (!(m->k_lo[i] <= m->k_hi[i])) return PIMC_ERR_ARG;
   std::memset(&a, 0, sizeof(a));
   a.dt = m->dt;
   a.Ro = m->Ro;
@@ -107,6 +122,11 @@ int model_args(const pimc_model* m, ModelArgs& a) {
   }
   a.p_mask = m->p_mask;
   a.proposal = m->proposal;
+  for (int i = 0; i < 12; ++i) {
+    a.k_lo[i] = m->k_lo[i];
+    a.k_hi[i] = m->k_hi[i];
+  }
+  a.k_mask = m->k_mask;
   return PIMC_OK;
 }
 
@@ -146,25 +166,47 @@ int ensure_batch(pimc_ctx* ctx, size_t B) {
 
 // Cross-tile workspace for `ntiles` tiles in total over `ngroups` windows:
 // boundary sites (two slots of 16 generation words per tile), double-buffered
-// parameter partials (70 generation words per tile), four sync words per
-// window (entry barrier and entry check).
+// parameter partials (70 generation words per tile), one entry word per tile.
+// New words start at generation 0 (cleared once here, never per call).
 int ensure_tilespace(pimc_ctx* c, size_t ntiles, size_t ngroups) {
   if (ntiles <= c->tile_cap && ngroups <= c->group_cap) return PIMC_OK;
   if (c->halo && hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
   ntiles = std::max(ntiles, c->tile_cap);
   ngroups = std::max(ngroups, c->group_cap);
-  void** bufs[] = {&c->halo, (void**)&c->wpart, (void**)&c->wsync};
+  void** bufs[] = {&c->halo, (void**)&c->wpart, (void**)&c->tsync};
   for (void** q : bufs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
   c->tile_cap = c->group_cap = 0;
-  const bool ok = hipMalloc(&c->halo, ntiles * 2 * 16 * sizeof(uint64_t)) == hipSuccess &&
-                  hipMalloc(&c->wpart, 2 * ntiles * 70 * sizeof(uint64_t)) == hipSuccess &&
-                  hipMalloc(&c->wsync, ngroups * 4 * sizeof(uint32_t)) == hipSuccess;
-  if (!ok) return PIMC_ERR_NOMEM;
+  const size_t sz[] = {ntiles * 2 * 16 * sizeof(uint64_t), 2 * ntiles * 70 * sizeof(uint64_t),
+                       ntiles * sizeof(uint64_t)};
+  for (int i = 0; i < 3; ++i) {
+    if (hipMalloc(bufs[i], sz[i]) != hipSuccess) return PIMC_ERR_NOMEM;
+    if (hipMemset(*bufs[i], 0, sz[i]) != hipSuccess) return PIMC_ERR_HIP;
+  }
+  // the clears must be complete before any stream of the caller runs a tile
+  if (hipDeviceSynchronize() != hipSuccess) return PIMC_ERR_HIP;
   c->tile_cap = ntiles;
   c->group_cap = ngroups;
+  c->gen_next = 0;
+  return PIMC_OK;
+}
+
+// Generation base of a tiled call of n sweeps on `stream`.  The 32-bit
+// generations are cleared (in stream order) only when they would wrap.
+int tile_generations(pimc_ctx* c, int64_t n, hipStream_t s, uint32_t& gen0, int per_sweep = 1) {
+  const uint64_t need = (uint64_t)n * (uint64_t)per_sweep + 4;
+  if (n > PIMC_MAX_TILED_SWEEPS) return PIMC_ERR_ARG;
+  if (c->gen_next + need > 0xFFFFFFFFull) {
+    int r = pimc::clear_words(c->halo, c->tile_cap * 2 * 16 * 2, s);
+    if (!r) r = pimc::clear_words(c->wpart, 2 * c->tile_cap * 70 * 2, s);
+    if (!r) r = pimc::clear_words(c->tsync, c->tile_cap * 2, s);
+    if (r) return r;
+    c->gen_next = 0;
+  }
+  gen0 = (uint32_t)c->gen_next;
+  c->gen_next += need;
   return PIMC_OK;
 }
 
@@ -323,7 +365,7 @@ void pimc_ctx_destroy(pimc_ctx* ctx) {
   if (ctx->blockK) (void)hipFree(ctx->blockK);
   if (ctx->halo) (void)hipFree(ctx->halo);
   if (ctx->wpart) (void)hipFree(ctx->wpart);
-  if (ctx->wsync) (void)hipFree(ctx->wsync);
+  if (ctx->tsync) (void)hipFree(ctx->tsync);
   void* hbufs[] = {ctx->hQ1, ctx->hR0, ctx->hR1, ctx->hX0, ctx->hpart, ctx->hp0, ctx->hpbuf, ctx->hrpbuf,
                    ctx->hH0, ctx->hdH, ctx->hout, ctx->hacc, ctx->hoff, ctx->hbmap, ctx->hbfirst, ctx->hk};
   for (void* q : hbufs)
@@ -385,9 +427,52 @@ int pimc_action(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, d
   a.p = path->p;
   a.y = path->y;
   a.I = path->I;
+  a.kin = path->kin;
   a.partial = ctx->partial;
   a.out = out3;
   return pimc::launch_action(a, path->prec == PIMC_FP64, (hipStream_t)stream);
+}
+
+int pimc_model_errors(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, double* esum, double* esq,
+                      void* stream) {
+  if (!ctx || !path || !esum || !esq || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
+  if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  pimc::ErrArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  a.M = path->M;
+  a.X = path->X;
+  a.p = path->p;
+  a.y = path->y;
+  a.I = path->I;
+  a.kin = path->kin;
+  a.esum = esum;
+  a.esq = esq;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  return pimc::launch_errors(a, path->prec == PIMC_FP64, (hipStream_t)stream);
+}
+
+int pimc_forecast(pimc_ctx* ctx, const pimc_model* model, int32_t B, const double* x0, const double* p,
+                  const double* kin, const double* I, int64_t N, double noise, uint64_t seed, int64_t member0,
+                  double* out, void* stream) {
+  if (!ctx || B < 1 || N < 0 || !x0 || !p || !I || !out || !(noise >= 0.0) || member0 < 0) return PIMC_ERR_ARG;
+  pimc::FcstArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  a.B = B;
+  a.N = N;
+  a.x0 = x0;
+  a.p = p;
+  a.I = I;
+  a.kin = kin;
+  a.noise = noise;
+  a.seed = seed;
+  a.member0 = member0;
+  a.out = out;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
+  return pimc::launch_forecast(a, (hipStream_t)stream);
 }
 
 int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, void* gX, double* gp, void* stream) {
@@ -404,17 +489,41 @@ int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, voi
   a.p = path->p;
   a.y = path->y;
   a.I = path->I;
+  a.kin = path->kin;
   a.gX = gX;
   a.partial = ctx->partial;
   a.out = gp;
   return pimc::launch_grad(a, path->prec == PIMC_FP64, (hipStream_t)stream);
 }
 
-int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
-               int64_t n_sweeps, int32_t flags, const pimc_stats* stats, const pimc_debug* debug, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks of an initialization-phase state; fills the kernel arguments.
+int init_args(const pimc_init_phase* ip, pimc::SweepArgs& a) {
+  if (!(ip->beta0 > 0.0 && ip->beta0 <= 1.0) || ip->n_cool < 1 || ip->n_skip < 1 || ip->n_init < 0) return PIMC_ERR_ARG;
+  if (!(ip->alpha >= 0.0 && ip->alpha < 1e3) || !(ip->f_acc >= 0.0 && ip->f_acc <= 1.0)) return PIMC_ERR_ARG;
+  if (!ip->beta || !ip->site_scale || !ip->w_param || !ip->cnt_site || !ip->cnt_param) return PIMC_ERR_ARG;
+  a.ip_fbeta = std::pow(1.0 / ip->beta0, 1.0 / (double)ip->n_cool);   // eq. fbeta
+  a.ip_ninit = ip->n_init;
+  a.ip_nskip = ip->n_skip;
+  a.ip_facc = ip->f_acc;
+  a.ip_alpha = ip->alpha;
+  a.ip_beta = ip->beta;
+  a.ip_scale = ip->site_scale;
+  a.ip_wpar = ip->w_param;
+  a.ip_cnt = ip->cnt_site;
+  a.ip_cntp = ip->cnt_param;
+  return PIMC_OK;
+}
+
+int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
+               int64_t n_sweeps, int32_t flags, const pimc_init_phase* ip, const pimc_stats* stats,
+               const pimc_debug* debug, void* stream) {
   if (!ctx || !path || !w || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
   if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
-  if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
+  if (n_sweeps < 0 || !valid_flags(flags)) return PIMC_ERR_ARG;
   if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
   if (stats && stats->batch && (!stats->sum || stats->nbatch < 1)) return PIMC_ERR_ARG;
   if (n_sweeps == 0) return PIMC_OK;
@@ -434,7 +543,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   a.ngroups = 1;
   a.halo = ctx->halo;
   a.wpart = ctx->wpart;
-  a.wsync = ctx->wsync;
+  a.tsync = ctx->tsync;
   a.spin_ticks = ctx->spin_ticks;
   a.offsets = nullptr;
   a.M_single = path->M;
@@ -454,6 +563,7 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.xref = stats->xref;
     a.ptrace = stats->ptrace;
     a.acc = stats->acc;
+    a.kacc = stats->kacc;
     a.burn = stats->burn;
     a.stride = stats->stride > 1 ? stats->stride : 1;
     fill_batch(a, stats->batch, stats->nbatch, (int64_t)rng.sweep0, n_sweeps, (path->M + 1) * 4);
@@ -461,7 +571,38 @@ int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   fill_debug(a, debug);
   a.err = ctx->err;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
-  return pimc::launch_sweep(a, fp64, K, T, NT, (hipStream_t)stream);
+  const bool kinetic = (flags & PIMC_KINETIC) != 0;
+  if (kinetic && !path->kin) return PIMC_ERR_ARG;
+  a.kin = path->kin;
+  if (debug) {
+    a.dbg_kprop = debug->kprop;
+    a.dbg_kdA = debug->kdA;
+    a.dbg_kacc = debug->kaccept;
+  }
+  const bool ext = ip || kinetic;
+  if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
+  if (ip && (r = init_args(ip, a))) return r;
+  // all-reduces between the tiles per sweep: the parameter statistics and
+  // one per sampled kinetic constant
+  const int per_sweep = 1 + (kinetic ? __builtin_popcount(a.m.k_mask) : 0);
+  if (T > 1 && (r = tile_generations(ctx, n_sweeps, (hipStream_t)stream, a.gen0, per_sweep))) return r;
+  return pimc::launch_sweep(a, fp64, K, T, NT, (hipStream_t)stream, ext);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimc_sweep(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
+               int64_t n_sweeps, int32_t flags, const pimc_stats* stats, const pimc_debug* debug, void* stream) {
+  return sweep_impl(ctx, model, path, rng, w, n_sweeps, flags, nullptr, stats, debug, stream);
+}
+
+int pimc_sweep_init(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
+                    int64_t n_sweeps, int32_t flags, const pimc_init_phase* init, const pimc_stats* stats,
+                    void* stream) {
+  if (!init) return PIMC_ERR_ARG;
+  return sweep_impl(ctx, model, path, rng, w, n_sweeps, flags, init, stats, nullptr, stream);
 }
 
 int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng, const double* w,
@@ -526,7 +667,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
                    const double* w, int64_t n_sweeps, int32_t flags, const pimc_batch_stats* stats, void* stream) {
   if (!ctx || !b || !w || !b->offsets || !b->X || !b->p || !b->y || !b->I || !b->chain) return PIMC_ERR_ARG;
   if (b->B < 1 || (b->prec != PIMC_FP64 && b->prec != PIMC_FP32)) return PIMC_ERR_ARG;
-  if (n_sweeps < 0 || flags < 1 || flags > 3) return PIMC_ERR_ARG;
+  if (n_sweeps < 0 || !valid_flags(flags) || (flags & PIMC_KINETIC)) return PIMC_ERR_ARG;   // no kin in a batch
   if (stats && (stats->sum || stats->sumsq) && (!stats->xref || !stats->sum)) return PIMC_ERR_ARG;
   if (stats && stats->batch && (!stats->sum || stats->nbatch < 1)) return PIMC_ERR_ARG;
   if (n_sweeps == 0) return PIMC_OK;
@@ -571,8 +712,8 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   if (T > 1) {
     if ((r = ensure_tilespace(ctx, (size_t)B * T, (size_t)B))) return r;
     a.halo = ctx->halo;
-      a.wpart = ctx->wpart;
-    a.wsync = ctx->wsync;
+    a.wpart = ctx->wpart;
+    a.tsync = ctx->tsync;
     a.spin_ticks = ctx->spin_ticks;
   }
   // longest windows first, so the tail of the launch holds the short ones
@@ -638,6 +779,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     fill_batch(a, stats->batch, stats->nbatch, (int64_t)sweep0, n_sweeps, b->offsets[B] * 4);
   }
   a.err = ctx->err;
+  if (T > 1 && (r = tile_generations(ctx, n_sweeps, s, a.gen0))) return r;
   if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s);
   return pimc::launch_sweep(a, fp64, K, B * T, NT, s);
 }
@@ -741,7 +883,15 @@ extern "C" int pimc_hmc(pimc_ctx* ctx, const pimc_model* model, const pimc_batch
     a.acc = stats->acc;
     a.ptrace = stats->ptrace;
     a.dHtrace = stats->dH;
+    const bool any = stats->traj_q || stats->traj_r || stats->traj_p || stats->traj_rp;
+    const bool all = stats->traj_q && stats->traj_r && stats->traj_p && stats->traj_rp;
+    if (any && !all) return PIMC_ERR_ARG;
+    a.tq = stats->traj_q;
+    a.tr = stats->traj_r;
+    a.tp = stats->traj_p;
+    a.trp = stats->traj_rp;
   }
+  a.S = (int64_t)S;
   a.ntrace = n_proposals;
   if (n_proposals == 1 || ctx->no_graphs) {
     for (int64_t q = 0; q < n_proposals; ++q)

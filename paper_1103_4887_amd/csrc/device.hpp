@@ -14,7 +14,7 @@ namespace pimc {
 // depends on (seed, chain), which are uniform over a workgroup, so the Weyl
 // additions land on the scalar unit; each round costs two 32x32->64 products.
 // ---------------------------------------------------------------------------
-enum : uint32_t { TAG_SITE = 1, TAG_SACC = 2, TAG_PARAM = 3, TAG_MOM = 4, TAG_PMOM = 5, TAG_HACC = 6 };
+enum : uint32_t { TAG_SITE = 1, TAG_SACC = 2, TAG_PARAM = 3, TAG_MOM = 4, TAG_PMOM = 5, TAG_HACC = 6, TAG_KIN = 7 };
 
 struct U4 {
   uint32_t x, y, z, w;
@@ -106,6 +106,8 @@ struct ModelArgs {
   double x_lo[4], x_hi[4], p_lo[7], p_hi[7];
   uint32_t p_mask;
   int32_t proposal;
+  double k_lo[12], k_hi[12];
+  uint32_t k_mask;
 };
 
 template <typename T>
@@ -135,6 +137,15 @@ struct Consts {
   }
   __device__ __forceinline__ void set_p(const double* pd) {
     for (int l = 0; l < 7; ++l) p[l] = (T)pd[l];
+  }
+  // Table 1 constants from kin [12], order (m, h, n) x (V_a, dV_a, tau0, tau1)
+  __host__ __device__ void set_gates(const double* kin) {
+    for (int g = 0; g < 3; ++g) {
+      Va[g] = (T)kin[4 * g];
+      inv_dVa[g] = (T)(1.0 / kin[4 * g + 1]);
+      tau0[g] = (T)kin[4 * g + 2];
+      tau1[g] = (T)kin[4 * g + 3];
+    }
   }
 };
 

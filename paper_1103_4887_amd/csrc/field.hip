@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(FIELD_BLOCK) action_partial_kernel(FieldArgs a
   Consts<double> C;
   C.init(a.m);
   C.set_p(a.p);
+  if (a.kin) C.set_gates(a.kin);
   double v[2] = {0.0, 0.0};
   if (n >= 1 && n <= a.M) {
     const T* X = (const T*)a.X;
@@ -136,6 +137,7 @@ __global__ void __launch_bounds__(FIELD_BLOCK) grad_partial_kernel(FieldArgs a) 
   Consts<T> C;
   C.init(a.m);
   C.set_p(a.p);
+  if (a.kin) C.set_gates(a.kin);
   double gp[7] = {0, 0, 0, 0, 0, 0, 0};
   if (n <= M) {
     const T* X = (const T*)a.X;

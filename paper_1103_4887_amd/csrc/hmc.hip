@@ -336,6 +336,13 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
         rp_out[l] = rps[l];
         p_out[l] = ps[l];
       }
+      if (a.tp) {
+#pragma unroll
+        for (int l = 0; l < 7; ++l) {
+          a.tp[((int64_t)s * a.B + ch) * 7 + l] = ps[l];
+          a.trp[((int64_t)s * a.B + ch) * 7 + l] = rps[l];
+        }
+      }
       if (out) atomicOr(&a.outside[ch], 1u);
     }
     if (s == 1 && b == a.bfirst[ch]) {
@@ -443,6 +450,15 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
     T* Rout = (T*)((s & 1) ? a.R1 : a.R0) + base * 4;
 #pragma unroll
     for (int c = 0; c < 4; ++c) Rout[(int64_t)n * 4 + c] = rn[c];
+    if (a.tq) {
+      T* tq = (T*)a.tq + ((int64_t)s * a.S + base + n) * 4;
+      T* tr = (T*)a.tr + ((int64_t)s * a.S + base + n) * 4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        tq[c] = x[c];
+        tr[c] = rn[c];
+      }
+    }
     if (MODE != 0) {
       T* Qout = (T*)((s & 1) ? a.Q1 : a.X) + base * 4;
 #pragma unroll
@@ -510,6 +526,10 @@ __global__ void __launch_bounds__(HB) hmc_step_kernel(HmcArgs a, int s) {
       const bool on = (a.m.p_mask >> l) & 1;
       rp0[l] = on ? z[l] / sqrt(a.minv[4 + l]) : 0.0;
       a.p0[(int64_t)ch * 7 + l] = ps[l];
+      if (a.tp) {
+        a.tp[(int64_t)ch * 7 + l] = ps[l];
+        a.trp[(int64_t)ch * 7 + l] = rp0[l];
+      }
     }
     a.outside[ch] = 0u;
   }
@@ -536,6 +556,7 @@ __global__ void __launch_bounds__(HB) hmc_finish_kernel(HmcArgs a, int L) {
     const bool on = (a.m.p_mask >> l) & 1;
     const double r = on ? rpL[l] - 0.5 * a.eps * gp[l] : 0.0;
     Kp += 0.5 * r * r * a.minv[4 + l];
+    if (a.trp) a.trp[((int64_t)(L + 1) * a.B + ch) * 7 + l] = r;
   }
   const double H1 = Ao + a.m.beta * Ad + Ks + Kp;
   const double dH = H1 - a.H0[ch];

@@ -47,6 +47,15 @@ struct HmcArgs {
   double* ptrace;          // [B][ntrace][7]
   double* dHtrace;         // [B][ntrace]
   int64_t ntrace;
+  // trajectory of the last proposal (nullable): after leapfrog kernel s,
+  // positions q(s) and momenta r(s+1/2) (r(L) after the last) in
+  // tq, tr [L+1][S][4] (path precision); p(s) in tp [L+1][B][7] and the
+  // parameter momenta rp(0), rp(s-1/2) (s = 1..L), rp(L) in trp [L+2][B][7]
+  void* tq;
+  void* tr;
+  double* tp;
+  double* trp;
+  int64_t S;               // packed sites of the batch
 };
 
 int launch_hmc_proposal(const HmcArgs& a, bool fp64, int L, hipStream_t s);

@@ -34,6 +34,7 @@ struct SweepArgs {
   const void* xref;
   double* ptrace;
   int64_t* acc;
+  int64_t* kacc;      // [12] accepted moves of the Table 1 constants (nullable)
   int64_t burn;
   int64_t stride;     // statistics every stride-th sweep from burn on
   int32_t stage;      // sites per LDS staging chunk of the statistics pass
@@ -49,21 +50,41 @@ struct SweepArgs {
   double* dbg_pprop;
   double* dbg_pdA;
   uint8_t* dbg_pacc;
+  double* dbg_kprop;   // kinetic moves of the last sweep (extended kernels)
+  double* dbg_kdA;
+  uint8_t* dbg_kacc;
+  double* kin;         // [12] Table 1 constants of the window (nullable: the model's), in/out
   uint32_t* err;  // bit 0: non-finite dA met, bit 1: entry state outside box, bit 2: wait timed out
   // time tiles (tiles == 1: a window is one workgroup, no global memory sync)
   int32_t tiles;
   int32_t ngroups;     // number of windows in the launch
   void* halo;          // [ngroups*tiles][2][16] generation words: first / last boundary site
   void* wpart;         // [2][ngroups][tiles][70] generation words: partial sums of the parameter statistics
-  uint32_t* wsync;     // [ngroups][4]: arrival counter, entry-check flag
+  uint64_t* tsync;     // [ngroups*tiles] generation words: a tile's entry (payload: its entry check failed)
+  uint32_t gen0;       // exchange generations of this call are gen0 + 1 .. gen0 + n_sweeps + 2
   uint64_t spin_ticks; // wall-clock ticks a wait may last
+  // initialization phase (Section 4.2; used by the INIT kernels only)
+  double ip_fbeta;     // beta grows by this factor after every sweep, capped at 1
+  int64_t ip_ninit;    // steps are adjusted at sweeps k < ip_ninit ...
+  int64_t ip_nskip;    // ... with (k + 1) % ip_nskip == 0
+  double ip_facc, ip_alpha;
+  double* ip_beta;     // [1] beta of the next sweep (in/out)
+  double* ip_scale;    // [sites] per-site factor of the state steps (in/out)
+  double* ip_wpar;     // [7] parameter steps (in/out)
+  int32_t* ip_cnt;     // [sites] accepted site moves since the last adjustment (in/out)
+  int32_t* ip_cntp;    // [7] accepted parameter moves since the last adjustment (in/out)
 };
 
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage);
 constexpr size_t LDS_BYTES = 160 * 1024;       // LDS per CU on gfx950
 constexpr size_t LDS_STATIC_RESERVE = 1024;    // kept free for the kernels' static LDS
 int sweep_max_threads(bool fp64, int K);
-int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s);
+// init: run the extended kernels (initialization phase, kinetic constants;
+// shapes of at most 256 threads; only the kinetic debug record)
+int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, bool init = false);
+// Clear n 32-bit words of device memory in stream order (a kernel: the call
+// may be recorded into a graph).
+int clear_words(void* p, size_t n, hipStream_t s);
 
 struct FieldArgs {  // action / gradient of one window
   ModelArgs m;
@@ -72,6 +93,7 @@ struct FieldArgs {  // action / gradient of one window
   const double* p;
   const void* y;
   const void* I;
+  const double* kin;  // [12] Table 1 constants (nullable: the model's)
   void* gX;         // gradient output (path precision), nullable
   double* partial;  // [nblocks][8] workspace
   double* out;      // action: [3]; gradient: gp [7]
@@ -81,5 +103,34 @@ constexpr int FIELD_BLOCK = 256;
 int launch_action(const FieldArgs& a, bool fp64, hipStream_t s);
 int launch_grad(const FieldArgs& a, bool fp64, hipStream_t s);
 inline int64_t field_blocks(int64_t M) { return (M + 1 + FIELD_BLOCK - 1) / FIELD_BLOCK; }
+
+struct ErrArgs {   // model and observation errors of one path, accumulated
+  ModelArgs m;
+  int64_t M;
+  const void* X;
+  const double* p;
+  const void* y;
+  const void* I;
+  const double* kin;
+  double* esum;     // [M][5]: eps (4 components), delta
+  double* esq;      // [M][5]
+};
+
+struct FcstArgs {   // forecast ensemble (FP64)
+  ModelArgs m;
+  int32_t B;
+  int64_t N;
+  const double* x0;  // [B][4]
+  const double* p;   // [B][7]
+  const double* I;   // [N+1]
+  const double* kin;
+  double noise;
+  uint64_t seed;
+  int64_t member0;
+  double* out;       // [B][N+1][4]
+};
+
+int launch_errors(const ErrArgs& a, bool fp64, hipStream_t s);
+int launch_forecast(const FcstArgs& a, hipStream_t s);
 
 }  // namespace pimc

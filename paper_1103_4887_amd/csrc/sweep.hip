@@ -89,34 +89,6 @@ __device__ __forceinline__ bool accept_u(uint32_t uword, double dA) {
   return ::log(u01_d(uword)) < -dA;
 }
 
-// Spin until *p >= target (agent-scope acquire).  Every wait is bounded: past
-// `ticks` of the constant wall clock the error flag gets bit 2 and the wait
-// gives up, so a workgroup can never wait forever on a missing partner.
-__device__ __forceinline__ void wait_ge(uint32_t* p, uint32_t target, uint32_t* err, uint64_t ticks) {
-  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
-      !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u)) {
-    const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (wall_clock64() - t0 > ticks) {
-        atomicOr(err, 4u);
-        break;
-      }
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-// Barrier across the tiles of one window: a monotonic arrival counter.
-__device__ __forceinline__ void tile_barrier(uint32_t* cnt, uint32_t target, uint32_t* err, uint64_t ticks) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    wait_ge(cnt, target, err, ticks);
-  }
-  __syncthreads();
-}
-
 // One Metropolis site update.  Returns true on accept (x, F replaced).
 template <typename T>
 __device__ __forceinline__ bool site_update(const Consts<T>& C, const T (&w)[4], bool uniform_prop,
@@ -277,10 +249,12 @@ __device__ __forceinline__ void site_publish(uint64_t* slot, const T (&x)[4], co
 }
 
 // Wait for generation `gen` of a published boundary site and read it (dV/dt
-// recomputed with the current parameters, as for an LDS neighbour).
+// recomputed with the current parameters, as for an LDS neighbour; the
+// gates' fields too when `gates`, i.e. when the Table 1 constants may have
+// moved since the site was published).
 template <typename T>
 __device__ __forceinline__ void site_fetch(const Consts<T>& C, const uint64_t* slot, uint32_t gen, T I, Nb<T>& nb,
-                                           uint32_t* err, uint64_t ticks) {
+                                           uint32_t* err, uint64_t ticks, bool gates) {
   constexpr int N = sizeof(T) == 4 ? 7 : 14;
   const uint64_t* src[N];
 #pragma unroll
@@ -301,6 +275,23 @@ __device__ __forceinline__ void site_fetch(const Consts<T>& C, const uint64_t* s
   nb.F[2] = v[5];
   nb.F[3] = v[6];
   nb.F[0] = hh_FV(C, nb.x[0], nb.x[1], nb.x[2], nb.x[3], I);
+  if (gates) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) nb.F[1 + g] = hh_Fgate(C, g, nb.x[0], nb.x[1 + g]);
+  }
+}
+
+// Gate equation of Section 5.1 in FP64 with the constants (V_a, dV_a, tau0,
+// tau1) of one gate: (a_inf(V) - a) / tau(V).
+__device__ __forceinline__ double gate_field64(double V, double a, const double (&gk)[4]) {
+  const double t = ::tanh((V - gk[0]) / gk[1]);
+  return (0.5 + 0.5 * t - a) / (gk[2] + gk[3] * (1.0 - t * t));
+}
+
+// Component 1 + g (the gate g) of a site state, by selects.
+template <typename T>
+__device__ __forceinline__ T sel_gate(const T (&x)[4], int g) {
+  return g == 0 ? x[1] : (g == 1 ? x[2] : x[3]);
 }
 
 // Hide a value from loop-invariant code motion.  Without it the compiler
@@ -411,6 +402,93 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double
   }
 }
 
+// log P(Z > z) of a standard normal, z >= 0, through the scaled
+// complementary error function (no underflow however far out z lies).
+__device__ __forceinline__ double log_upper_tail(double z) {
+  return ::log(0.5 * erfcx(z * 0.70710678118654752440)) - 0.5 * z * z;
+}
+
+// The u-quantile of Z given a <= Z <= b, 0 <= a < b <= inf: solves
+// log P(Z > z) = log P(Z > a) + log(1 - u (1 - P(Z > b) / P(Z > a))) by
+// Newton steps from z = a.  log P(Z > z) is concave and decreasing, so the
+// first step lands right of the root and the rest descend onto it
+// (quadratically); twelve steps reach full precision from any start.
+__device__ __forceinline__ double upper_tail_quantile(double a, double b, double u) {
+  const double la = log_upper_tail(a);
+  const double r = b < 1e300 ? ::exp(log_upper_tail(b) - la) : 0.0;
+  const double T = la + (u < 0.5 ? ::log1p(-u * (1.0 - r)) : ::log((1.0 - u) + u * r));
+  double z = a;
+  for (int it = 0; it < 12; ++it)
+    z += (log_upper_tail(z) - T) * erfcx(z * 0.70710678118654752440) * 1.25331413731550025121;  // sqrt(pi/2)
+  return z;
+}
+
+// The u-quantile of N(mu, sg^2) truncated to [lo, hi].  A box that holds
+// the mean inverts the normal CDF directly; a box entirely on one side of
+// it goes through the upper-tail quantile above (mirrored for a box below
+// the mean), which stays exact when the box lies many standard deviations
+// out, where the CDF itself underflows.  Not inlined: the seven calls of a
+// sweep share one copy.
+__device__ __attribute__((noinline)) double trunc_normal_inv(double mu, double sg, double lo, double hi, double u) {
+  const double za = (lo - mu) / sg, zb = (hi - mu) / sg;
+  if (za >= 0.0) return mu + sg * upper_tail_quantile(za, zb, u);
+  if (zb <= 0.0) return mu - sg * upper_tail_quantile(-zb, -za, 1.0 - u);
+  const double pa = normcdf(za), pb = normcdf(zb);
+  return mu + sg * normcdfinv(pa + u * (pb - pa));
+}
+
+// Exact conditional draw of parameter L given the path and the other
+// parameters.  The action is quadratic in p_L: with q = d theta / d p_L,
+// A(p_L + d) - A(p_L) = cA (d^2 q^T G q - 2 d q . s), so p_L given the rest
+// is N(p_L + q.s / q^T G q, 1 / (2 cA q^T G q)) truncated to its box (drawn
+// uniformly on the box when the curvature is not positive).  ug: the
+// uniform of the draw.  The statistics follow the move as for an accepted
+// Metropolis step.
+template <int L, bool DBG>
+__device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, double cA, double (&pd)[7],
+                                            double (&s)[7], const double (&G)[28], bool& changed, int& acc,
+                                            int& nonfin, bool rec, int win) {
+  if (!((a.m.p_mask >> L) & 1)) return;
+  constexpr int ia = ThetaMove<L>::ia;
+  constexpr int ib = ThetaMove<L>::ib;
+  constexpr int ibb = ib >= 0 ? ib : 0;
+  constexpr bool prod = L == 2 || L == 4 || L == 6;   // theta_L = p_{L-1} p_L
+  const double qa = prod ? pd[prod ? L - 1 : 0] : 1.0;
+  const double qb = ib >= 0 ? pd[ibb] : 0.0;
+  double qGq = qa * qa * G[symi(ia, ia)];
+  double qs = qa * s[ia];
+  if (ib >= 0) {
+    qGq += 2.0 * qa * qb * G[symi(ia, ibb)] + qb * qb * G[symi(ibb, ibb)];
+    qs += qb * s[ibb];
+  }
+  const double lo = a.m.p_lo[L], hi = a.m.p_hi[L];
+  const double curv = cA * qGq;
+  double v;
+  if (curv > 0.0 && __builtin_isfinite(curv))
+    v = trunc_normal_inv(pd[L] + qs / qGq, 1.0 / sqrt(2.0 * curv), lo, hi, ug);
+  else
+    v = lo + ug * (hi - lo);
+  const bool ok = __builtin_isfinite(v);
+  nonfin += ok ? 0 : 1;
+  v = ok ? fmin(fmax(v, lo), hi) : pd[L];
+  const double dp = v - pd[L];
+  const double da = qa * dp, db = qb * dp;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    double gs = G[symi(j, ia)] * da;
+    if (ib >= 0) gs += G[symi(j, ibb)] * db;
+    s[j] -= gs;
+  }
+  pd[L] = v;
+  changed = changed || dp != 0.0;
+  acc += ok ? 1 : 0;
+  if (DBG && rec) {
+    if (a.dbg_pprop) a.dbg_pprop[win * 7 + L] = v;
+    if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = __builtin_nan("");
+    if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
+  }
+}
+
 }  // namespace
 
 // The sweep of one workgroup (a window, or one time tile of it) with K
@@ -418,7 +496,7 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double
 // kernel for the launch's K and, for launches of 16 sites per thread, a
 // device function for each smaller K that a window of a batch may use; the
 // kernels of every other shape are the statements alone.
-template <typename T, int K, int MAXT, bool DBG>
+template <typename T, int K, int MAXT, bool DBG, bool EXT>
 __device__ __forceinline__ void sweep_body(SweepArgs a) {
 #include "sweep_body.inc"
 }
@@ -427,20 +505,20 @@ __device__ __forceinline__ void sweep_body(SweepArgs a) {
 // blockK[b] sites per thread (4, 8, 12 or the launch's 16: the fewest that
 // its workgroup holds), so a short window's workgroup is done in proportion
 // to its length rather than as late as the longest window's.
-template <typename T, int K, int MAXT, bool DBG>
+template <typename T, int K, int MAXT, bool DBG, bool EXT>
 __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
-  if constexpr (K == 16 && sizeof(T) == 4) {
+  if constexpr (K == 16 && sizeof(T) == 4 && !EXT) {
     const int kb = a.blockK ? (int)a.blockK[blockIdx.x] : K;
     if (kb == 4) {
-      sweep_body<T, 4, MAXT, DBG>(a);
+      sweep_body<T, 4, MAXT, DBG, EXT>(a);
       return;
     }
     if (kb == 8) {
-      sweep_body<T, 8, MAXT, DBG>(a);
+      sweep_body<T, 8, MAXT, DBG, EXT>(a);
       return;
     }
     if (kb == 12) {
-      sweep_body<T, 12, MAXT, DBG>(a);
+      sweep_body<T, 12, MAXT, DBG, EXT>(a);
       return;
     }
   }
@@ -454,9 +532,15 @@ size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
          16 * sizeof(int) + (size_t)stage * 4 * ts;
 }
 
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void zero_u32_kernel(uint32_t* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
+}
+
+int clear_words(void* p, size_t n, hipStream_t s) {
+  if (!n) return PIMC_OK;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }
 
 // The launch is refused on the host (never enqueued) when the kernel's static
@@ -470,74 +554,64 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
   if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
   if (a.tiles > 1) {
-    // tiles wait on each other, so all of them must be resident: a shape
-    // the device cannot hold at once is refused before anything is enqueued
+    // tiles wait on each other, so all of them must be resident at once: a
+    // shape the device cannot hold is refused before anything is enqueued
     int per_cu = 0, ncu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, NT, sm) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return PIMC_ERR_HIP;
     if ((int64_t)per_cu * ncu < nblocks) return PIMC_ERR_UNSUPPORTED;
-    // reset the exchange words (generation 0) and the entry counters in
-    // stream order, then launch cooperatively
-    const int nh = nblocks * 2 * SLOT_WORDS * 2, np = 2 * nblocks * 2 * NRED * 2, nw = a.ngroups * 4;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((nh + 255) / 256), dim3(256), 0, s, (uint32_t*)a.halo, nh);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((np + 255) / 256), dim3(256), 0, s, (uint32_t*)a.wpart, np);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, a.wsync, nw);
-    SweepArgs copy = a;
-    void* args[] = {&copy};
-    const hipError_t e = hipLaunchCooperativeKernel((const void*)k, dim3(nblocks), dim3(NT), args, (unsigned)sm, s);
-    if (e == hipErrorCooperativeLaunchTooLarge) {
-      (void)hipGetLastError();   // leave no stale error for the caller's next runtime call
-      return PIMC_ERR_UNSUPPORTED;
-    }
-    return e == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
+    // every tile is resident once launched (checked above): the waits
+    // between tiles are bounded, so a tile that cannot be placed (other
+    // work holding the CUs) ends the launch with a timeout, never a hang
   }
   hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), sm, s, a);
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }
 
-#define PIMC_SWEEP_LAUNCH(T, K, MAXT)                                                \
-  do {                                                                               \
-    if (dbg)                                                                         \
-      return launch_checked(sweep_kernel<T, K, MAXT, true>, nblocks, NT, sm, s, a);  \
-    else                                                                             \
-      return launch_checked(sweep_kernel<T, K, MAXT, false>, nblocks, NT, sm, s, a); \
-  } while (0)
+// One launch shape: the extended kernel (initialization phase, kinetic
+// constants; one wave per SIMD shapes only) when asked for, the debug kernel
+// when a debug record is, else the plain kernel.
+template <typename T, int K, int MAXT>
+static int launch_shape(const SweepArgs& a, bool dbg, bool init, int nblocks, int NT, size_t sm, hipStream_t s) {
+  if (init) {
+    if constexpr (MAXT <= 256) {
+      return launch_checked(sweep_kernel<T, K, MAXT, false, true>, nblocks, NT, sm, s, a);
+    } else {
+      return PIMC_ERR_UNSUPPORTED;
+    }
+  }
+  if (dbg) return launch_checked(sweep_kernel<T, K, MAXT, true, false>, nblocks, NT, sm, s, a);
+  return launch_checked(sweep_kernel<T, K, MAXT, false, false>, nblocks, NT, sm, s, a);
+}
 
 // Launch bounds follow the thread count: up to 256 threads (one wave per
 // SIMD) a wave may hold 512 registers (architectural + accumulation), so the
 // register-resident path never spills to scratch.
-#define PIMC_SWEEP_PICK(T, K, BIG)          \
-  do {                                      \
-    if (NT <= 256)                          \
-      PIMC_SWEEP_LAUNCH(T, K, 256);         \
-    else                                    \
-      PIMC_SWEEP_LAUNCH(T, K, BIG);         \
-  } while (0)
+template <typename T, int K, int BIG>
+static int launch_pick(const SweepArgs& a, bool dbg, bool init, int nblocks, int NT, size_t sm, hipStream_t s) {
+  if (NT <= 256) return launch_shape<T, K, 256>(a, dbg, init, nblocks, NT, sm, s);
+  return launch_shape<T, K, BIG>(a, dbg, init, nblocks, NT, sm, s);
+}
 
-int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s) {
+int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, bool init) {
   const size_t sm = sweep_smem_bytes(NT, K, fp64, a.stage);
   if (sm + LDS_STATIC_RESERVE > LDS_BYTES || NT > sweep_max_threads(fp64, K)) return PIMC_ERR_UNSUPPORTED;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
+  if (init && dbg) return PIMC_ERR_UNSUPPORTED;   // extended kernels record only the kinetic moves
   if (fp64) {
-    switch (K) {
-      case 4:
-        if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
-        PIMC_SWEEP_LAUNCH(double, 4, 256);
-      default: return PIMC_ERR_UNSUPPORTED;
-    }
-  } else {
-    switch (K) {
-      case 2:
-        if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // a tiling option: one wave per SIMD only
-        PIMC_SWEEP_LAUNCH(float, 2, 256);
-      case 4: PIMC_SWEEP_PICK(float, 4, 1024); break;
-      case 8: PIMC_SWEEP_PICK(float, 8, 512); break;
-      case 16: PIMC_SWEEP_PICK(float, 16, 512); break;
-      default: return PIMC_ERR_UNSUPPORTED;
-    }
+    if (K != 4 || NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
+    return launch_shape<double, 4, 256>(a, dbg, init, nblocks, NT, sm, s);
   }
-  return PIMC_ERR_UNSUPPORTED;
+  switch (K) {
+    case 2:
+      if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // a tiling option: one wave per SIMD only
+      return launch_shape<float, 2, 256>(a, dbg, init, nblocks, NT, sm, s);
+    case 4: return launch_pick<float, 4, 1024>(a, dbg, init, nblocks, NT, sm, s);
+    case 8: return launch_pick<float, 8, 512>(a, dbg, init, nblocks, NT, sm, s);
+    case 16: return launch_pick<float, 16, 512>(a, dbg, init, nblocks, NT, sm, s);
+    default: return PIMC_ERR_UNSUPPORTED;
+  }
 }
 
 int sweep_max_threads(bool fp64, int K) {

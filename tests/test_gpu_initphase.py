@@ -1,0 +1,156 @@
+"""The initialization phase (Section 4.2: annealing of beta, adjustment of
+the step sizes to the acceptance) of the HIP library against the oracle.
+
+FP64: whole chains in lockstep with the oracle's InitPhase, split over two
+calls so that the device state carries over: paths within 1e-9, parameters
+within 1e-10, beta, site step factors and parameter steps within 1e-12,
+acceptance counts exact.  FP32: the benchmark window's tiled launch shapes
+give the same chain and the same adjusted steps as one workgroup (the steps
+depend on integer counts only); a unit phase (beta0 = 1, no adjustment)
+reproduces pimc_sweep bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sampler as OS
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1103_4887_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _state(ip):
+    return (ip.beta.cpu().numpy()[0], ip.site_scale.cpu().numpy(), ip.w_param.cpu().numpy(),
+            ip.cnt_site.cpu().numpy(), ip.cnt_param.cpu().numpy())
+
+
+@pytest.mark.parametrize("M,mask", [(200, 0x7F), (257, 0x2A)])
+def test_init_phase_fp64_lockstep(ctx, M, mask):
+    spec = W.ModelSpec(p_mask=mask)
+    prob = W.make_hh_problem(M, 0.02, 141 + M, model=spec, require_spike=False, init="guess")
+    kw = dict(beta0=0.05, n_cool=60, n_init=120, n_skip=20, f_acc=0.23, alpha=0.05)
+    oi = OS.InitPhase(**kw).start(prob.M, prob.w_param)
+    X, p = prob.X0.copy(), prob.p0.copy()
+    ost = OS.Stats(prob.M, 4, 7, 150)
+    ctx.set_tiles(0)
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    gi = P.InitPhase.start(win, prob.w_param, **kw)
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    for sweep0, n in ((0, 100), (100, 50)):
+        st = OS.Stats(prob.M, 4, 7, n)
+        OS.run(spec, X, p, prob.y, prob.I, seed=prob.seed, chain=1, sweep0=sweep0, n_sweeps=n,
+               w_state=prob.w_state, w_param=prob.w_param, init=oi, stats=st)
+        gst = P.SweepStats.allocate(win, n, moments=False)
+        print(f"init phase fp64 M={M} sweeps {sweep0}..{sweep0 + n}", flush=True)
+        P.pimc_sweep_init(ctx, spec, win, seed=prob.seed, chain=1, sweep0=sweep0, w=w, n_sweeps=n, init=gi,
+                          stats=gst)
+        assert ctx.sync() == 0
+        np.testing.assert_array_equal(gst.acc.cpu().numpy(), st.acc)
+        np.testing.assert_allclose(gst.ptrace.cpu().numpy(), st.ptrace, rtol=1e-10)
+    beta, scale, wpar, cnt, cntp = _state(gi)
+    assert beta == pytest.approx(oi.beta, rel=1e-15) and beta == 1.0
+    np.testing.assert_allclose(scale, oi.site_scale, rtol=1e-12)
+    np.testing.assert_allclose(wpar, oi.w_param, rtol=1e-12)
+    np.testing.assert_array_equal(cnt, oi.cnt_site)
+    np.testing.assert_array_equal(cntp, oi.cnt_param)
+    np.testing.assert_allclose(win.X.cpu().numpy(), X, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(win.p.cpu().numpy(), p, rtol=1e-10)
+    assert np.abs(scale - 1.0).max() > 0.01       # the steps did move
+
+
+def test_init_phase_annealing_only_fp64(ctx):
+    """beta below 1 without step adjustment (n_init = 0): the sweeps are those
+    of the tempered action, in lockstep with the oracle."""
+    spec = W.ModelSpec(p_mask=0x7F)
+    prob = W.make_hh_problem(96, 0.02, 150, model=spec, require_spike=False, init="guess")
+    kw = dict(beta0=0.01, n_cool=30, n_init=0, n_skip=7)
+    oi = OS.InitPhase(**kw).start(prob.M, prob.w_param)
+    X, p = prob.X0.copy(), prob.p0.copy()
+    OS.run(spec, X, p, prob.y, prob.I, seed=3, chain=0, sweep0=0, n_sweeps=40, w_state=prob.w_state,
+           w_param=prob.w_param, init=oi)
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
+    gi = P.InitPhase.start(win, prob.w_param, **kw)
+    P.pimc_sweep_init(ctx, spec, win, seed=3, chain=0, sweep0=0, w=P.widths_tensor(prob.w_state, prob.w_param),
+                      n_sweeps=40, init=gi)
+    assert ctx.sync() == 0
+    np.testing.assert_allclose(win.X.cpu().numpy(), X, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(win.p.cpu().numpy(), p, rtol=1e-10)
+    np.testing.assert_array_equal(gi.site_scale.cpu().numpy(), np.ones(prob.M + 1))
+
+
+def test_unit_phase_equals_plain_sweep_fp32(ctx):
+    prob = W.config_problem("c2")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    a = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+    b = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+    ctx.set_tile(2)
+    ctx.set_tiles(16)
+    try:
+        P.pimc_sweep(ctx, prob.model, a, seed=9, chain=0, sweep0=0, w=w, n_sweeps=30)
+        gi = P.InitPhase.start(b, prob.w_param, beta0=1.0, n_cool=1, n_init=0, n_skip=1)
+        P.pimc_sweep_init(ctx, prob.model, b, seed=9, chain=0, sweep0=0, w=w, n_sweeps=30, init=gi)
+        assert ctx.sync() == 0
+    finally:
+        ctx.set_tile(0)
+        ctx.set_tiles(0)
+    np.testing.assert_array_equal(a.X.cpu().numpy(), b.X.cpu().numpy())
+    np.testing.assert_array_equal(a.p.cpu().numpy(), b.p.cpu().numpy())
+
+
+def test_init_phase_fp32_tiles_give_the_same_chain(ctx):
+    prob = W.config_problem("c2")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    kw = dict(beta0=0.02, n_cool=40, n_init=60, n_skip=10, alpha=0.05)
+    outs = []
+    for K, T in ((0, 0), (2, 16), (0, 4)):
+        ctx.set_tile(K)
+        ctx.set_tiles(T)
+        try:
+            win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+            gi = P.InitPhase.start(win, prob.w_param, **kw)
+            print(f"init phase fp32 K={K} T={T}", flush=True)
+            P.pimc_sweep_init(ctx, prob.model, win, seed=17, chain=0, sweep0=0, w=w, n_sweeps=80, init=gi)
+            assert ctx.sync() == 0
+        finally:
+            ctx.set_tile(0)
+            ctx.set_tiles(0)
+        outs.append((win.X.cpu().numpy(), win.p.cpu().numpy()) + _state(gi))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o[0], outs[0][0])
+        np.testing.assert_allclose(o[1], outs[0][1], rtol=1e-14)
+        assert o[2] == outs[0][2]
+        np.testing.assert_array_equal(o[3], outs[0][3])
+        np.testing.assert_allclose(o[4], outs[0][4], rtol=1e-14)
+        np.testing.assert_array_equal(o[5], outs[0][5])
+        np.testing.assert_array_equal(o[6], outs[0][6])
+
+
+def test_init_phase_refuses_wide_shapes_and_bad_state(ctx):
+    prob = W.config_problem("c2")
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    gi = P.InitPhase.start(win, prob.w_param, beta0=0.1, n_cool=10, n_init=10, n_skip=5)
+    ctx.set_tile(4)
+    ctx.set_tiles(1)          # one workgroup of 1024 threads: not an init-phase shape
+    try:
+        with pytest.raises(P._lib.PimcError) as e:
+            P.pimc_sweep_init(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1, init=gi)
+        assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
+    finally:
+        ctx.set_tile(0)
+        ctx.set_tiles(0)
+    bad = P.InitPhase.start(win, prob.w_param, beta0=0.0, n_cool=10, n_init=10, n_skip=5)
+    with pytest.raises(P._lib.PimcError) as e:
+        P.pimc_sweep_init(ctx, prob.model, win, seed=1, chain=0, sweep0=0, w=w, n_sweeps=1, init=bad)
+    assert e.value.status == P._lib.PIMC_ERR_ARG
+    assert ctx.sync() == 0

@@ -42,3 +42,20 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_ncore_oracle_leg_reports_cores_and_model():
+    """The N-core oracle leg of the benchmark runs one spawned process per
+    core (here at most 2, for a short budget) and reports what it used."""
+    import workloads as W
+
+    probs = [W.make_hh_problem(M, 0.02, 101 + M, require_spike=False) for M in (40, 64)]
+    old = bench.host_cores
+    bench.host_cores = lambda: 2
+    try:
+        r = bench.cpu_baseline_ncore("sweep", probs, 0.5)
+    finally:
+        bench.host_cores = old
+    assert r["cores"] == 2 and r["kind"] == "oracle"
+    assert r["value"] > 0 and r["unit"] == "site-updates/s"
+    assert r["cpu_model"] and "M from 40 to 64" in r["sample"]

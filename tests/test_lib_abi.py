@@ -44,12 +44,30 @@ def test_strerror_and_null_arguments():
     assert lib.pimc_set_sweep_tile(None, 4) == L.PIMC_ERR_ARG
 
 
-def test_struct_layout_matches_header():
-    # sizes fixed by the header's field order (all naturally aligned)
-    assert C.sizeof(L.Model) == 8 * (1 + 1 + 4 + 1 + 12 + 8 + 14) + 8
-    assert C.sizeof(L.Path) == 8 + 8 + 4 * 8
-    assert C.sizeof(L.Rng) == 24
-    assert C.sizeof(L.Stats) == 9 * 8
-    assert C.sizeof(L.BatchStats) == 9 * 8
-    assert C.sizeof(L.Debug) == 6 * 8
-    assert C.sizeof(L.Batch) == 8 + 6 * 8
+def test_struct_layout_matches_header(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets that
+    the C compiler gives the header's struct (compiled here with gcc)."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"pimc_model": L.Model, "pimc_path": L.Path, "pimc_rng": L.Rng, "pimc_stats": L.Stats,
+               "pimc_batch_stats": L.BatchStats, "pimc_debug": L.Debug, "pimc_batch": L.Batch,
+               "pimc_hmc_stats": L.HmcStats, "pimc_init_phase": L.InitPhase}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pimc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(L.HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

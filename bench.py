@@ -48,7 +48,8 @@ def parse():
                     help="sweeps (proposals for c5); default 100000 for one window, 2000 for c4, 300 for c5")
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--config", default="c2",
-                    help="c1-c3: one window; c4: the uneven batch; c5: HMC on 64 chains (default c2)")
+                    help="c1-c3: one window; c4: the uneven batch; c5: HMC on 64 chains; paper: the paper-like "
+                         "run of Section 5.1 with the model checks of Section 6 (default c2)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of each oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="sites per thread (0: autotune)")
@@ -462,6 +463,40 @@ def cpu_baseline_hmc(prob, tun, L, budget_s: float):
             "sample": f"{n} proposals of one M={prob.M} chain ({wall:.1f} s)"}
 
 
+def bench_paper(args):
+    """The paper-like run: Section 5.1's window (M = 8000 at 25 kHz, Ro = 100,
+    Lorenz-driven twin data), its schedule (1e6 iterations, N_skip = 400,
+    N_init = 5e5, annealing over 1e5 from beta0 = 0.01, f_acc = 0.23,
+    alpha = 0.02; --steps shortens it proportionally) and the model checks of
+    Section 6.  One step = one sweep of the whole window."""
+    import paper_1103_4887_amd as P
+    from paper_1103_4887_amd import replicate
+    from workloads.paper_data import PAPER_RUN, make_paper_problem
+
+    run = dict(PAPER_RUN)
+    if args.steps:
+        f = args.steps / run["sweeps"]
+        run = {**run, "sweeps": args.steps, "n_init": int(run["n_init"] * f), "n_cool": max(1, int(run["n_cool"] * f)),
+               "n_skip": max(1, int(run["n_skip"] * min(1.0, 10 * f)))}
+    prob = make_paper_problem(M=run["M"], dt=run["dt"], Ro=run["Ro"])
+    ctx = P.Context(0)
+    t0 = time.perf_counter()
+    out = replicate.run(ctx, prob, sweeps=run["sweeps"], n_init=run["n_init"], n_cool=run["n_cool"],
+                        n_skip=run["n_skip"], beta0=run["beta0"], f_acc=run["f_acc"], alpha=run["alpha"],
+                        verbose=True)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    sweeps = run["sweeps"]
+    return {"metric": "paper-like run (Section 5.1 schedule) with the model checks of Section 6, 1 GPU",
+            "value": (prob.M + 1) * sweeps / wall, "unit": "site-updates/s (whole run, wall clock)", "n_gpus": 1,
+            "steps": sweeps, "ms_per_step": wall * 1e3 / sweeps, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"HH M={prob.M}, dt={prob.model.dt} ms, Ro={prob.model.Ro}, Lorenz-driven drive "
+                                   f"({prob.meta['spikes']} spikes), uniform proposals, 7 parameters",
+                       **run},
+            "paper_gtx460_s_per_1e6_iterations": 683.0,
+            "wall_s": wall, "result": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -477,6 +512,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_seconds
+    if args.config == "paper":
+        print(json.dumps(bench_paper(args)), flush=True)
+        return
     if args.config in ("c4", "c5"):
         ctx = P.Context(0)
         if args.config == "c4":

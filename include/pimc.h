@@ -63,7 +63,9 @@ enum { PIMC_PROP_GAUSS = 0, PIMC_PROP_UNIFORM = 1 }; /* proposal law (Fig. 1 ste
  * p_l and the conditional is a Gaussian truncated to p_l's box, read from the
  * same path statistics the Metropolis moves use; the draw inverts its CDF
  * with word 0 of the parameter's Philox block.  It changes the chain, so it
- * is off unless asked for; acceptance counters then count finite draws. */
+ * is off unless asked for; acceptance counters then count finite draws.
+ * Runs in the launch shapes of at most 256 threads per workgroup (others
+ * return PIMC_ERR_UNSUPPORTED). */
 enum { PIMC_STATES = 1, PIMC_PARAMS = 2, PIMC_GIBBS = 4, PIMC_KINETIC = 8 };
 /* PIMC_KINETIC (pimc_sweep / pimc_sweep_init on a path with `kin` set): after
  * the parameters, each Table 1 constant selected by model->k_mask, in the
@@ -150,8 +152,9 @@ typedef struct {
  *   the box), accept [M+1] uint8; pprop/pdA [7] FP64, paccept [7] uint8
  *   (entries of unsampled parameters are left untouched); kprop/kdA [12]
  *   FP64, kaccept [12] uint8 for the Table 1 constants (PIMC_KINETIC).
- *   Calls with PIMC_KINETIC record only the three k fields (the others must
- *   be NULL). */
+ *   Calls with PIMC_KINETIC or PIMC_GIBBS record the parameter and k fields
+ *   only: xprop, dA and accept must then be NULL (else
+ *   PIMC_ERR_UNSUPPORTED).  A Gibbs draw records pdA = NaN. */
 typedef struct {
   void* xprop;
   double* dA;

@@ -187,10 +187,11 @@ class SweepDebug:
     kaccept: Optional[torch.Tensor] = None
 
     @staticmethod
-    def allocate(win: Window, sites: bool = True, kinetic: bool = False):
-        """Record of the last sweep: sites and parameters (sites=True) and/or
-        the kinetic constants (kinetic=True; calls with PIMC_KINETIC record
-        only those)."""
+    def allocate(win: Window, sites: bool = True, kinetic: bool = False, params: Optional[bool] = None):
+        """Record of the last sweep: the sites (sites=True), the parameter
+        moves (params; by default with the sites) and the kinetic constants
+        (kinetic=True).  Calls with PIMC_KINETIC or PIMC_GIBBS record the
+        parameters and kinetic constants only."""
         dev = win.X.device
         nan = float("nan")
         d = SweepDebug()
@@ -198,6 +199,7 @@ class SweepDebug:
             d.xprop = torch.full_like(win.X, nan)
             d.dA = torch.full((win.M + 1,), nan, dtype=torch.float64, device=dev)
             d.accept = torch.zeros(win.M + 1, dtype=torch.uint8, device=dev)
+        if sites if params is None else params:
             d.pprop = torch.full((7,), nan, dtype=torch.float64, device=dev)
             d.pdA = torch.full((7,), nan, dtype=torch.float64, device=dev)
             d.paccept = torch.zeros(7, dtype=torch.uint8, device=dev)

@@ -20,13 +20,16 @@ from .api import Context, Window, pimc_sweep
 _CACHE: Dict[Tuple[int, str, int], Tuple[int, int, float]] = {}
 
 
-def candidates(M: int, prec: str) -> Iterable[Tuple[int, int]]:
-    """(K, T) pairs worth timing; K = 0 / T = 0 mean the library's own choice."""
+def candidates(M: int, prec: str, narrow: bool = False) -> Iterable[Tuple[int, int]]:
+    """(K, T) pairs worth timing; K = 0 / T = 0 mean the library's own choice.
+    narrow: only shapes of at most 256 threads per workgroup (the automatic
+    choice and time tiles), the ones the extended kernels run in."""
     yield (0, 0)
     if prec == "fp64":
         return
-    for K in (4, 8, 16):
-        yield (K, 1)
+    if not narrow:
+        for K in (4, 8, 16):
+            yield (K, 1)
     for T in (2, 4, 8, 16, 32, 64, 128):
         if M // T >= 256:
             yield (0, T)
@@ -35,9 +38,11 @@ def candidates(M: int, prec: str) -> Iterable[Tuple[int, int]]:
 
 
 def tune(ctx: Context, spec, win: Window, w: torch.Tensor, *, flags: int = L.PIMC_STATES | L.PIMC_PARAMS,
-         sweeps: int = 200, seed: int = 12345, verbose: bool = False) -> Tuple[int, int, float]:
-    """Pick (K, T) for this window; applies it to ctx and returns (K, T, us_per_sweep)."""
-    key = (win.M, win.prec, flags)
+         sweeps: int = 200, seed: int = 12345, verbose: bool = False, narrow: bool = False) -> Tuple[int, int, float]:
+    """Pick (K, T) for this window; applies it to ctx and returns (K, T, us_per_sweep).
+    narrow: choose among the shapes the extended kernels run in (initialization
+    phase, kinetic constants)."""
+    key = (win.M, win.prec, flags, narrow)
     if key in _CACHE:
         K, T, us = _CACHE[key]
         ctx.set_tile(K)
@@ -45,7 +50,7 @@ def tune(ctx: Context, spec, win: Window, w: torch.Tensor, *, flags: int = L.PIM
         return K, T, us
     best: Optional[Tuple[int, int, float]] = None
     scratch = Window(X=win.X.clone(), p=win.p.clone(), y=win.y, I=win.I, prec=win.prec)
-    for K, T in candidates(win.M, win.prec):
+    for K, T in candidates(win.M, win.prec, narrow):
         ctx.set_tile(K)
         ctx.set_tiles(T)
         try:

@@ -34,7 +34,7 @@ struct pimc_ctx {
   // captured graph of the batched sweep launch, replayed with new arguments
   struct BatchGraph {
     bool valid = false;
-    bool fp64 = false, dbg = false;
+    bool fp64 = false, dbg = false, ext = false;
     int K = 0, NT = 0, nblocks = 0, stage = 0;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -579,7 +579,9 @@ int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.dbg_kdA = debug->kdA;
     a.dbg_kacc = debug->kaccept;
   }
-  const bool ext = ip || kinetic;
+  // initialization phase, kinetic constants and exact parameter draws run
+  // in the extended kernels (shapes of at most 256 threads)
+  const bool ext = ip || kinetic || (flags & PIMC_GIBBS);
   if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
   if (ip && (r = init_args(ip, a))) return r;
   // all-reduces between the tiles per sweep: the parameter statistics and
@@ -615,18 +617,18 @@ int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, p
 // stream with this call's arguments written into its kernel node.  (Tiled
 // batches launch cooperatively and are not captured.)
 static int launch_batch_graph(pimc_ctx* ctx, const pimc::SweepArgs& a, bool fp64, int K, int nblocks, int NT,
-                              int stage, hipStream_t s) {
+                              int stage, hipStream_t s, bool ext) {
   auto& bg = ctx->bgraph;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   int r = PIMC_OK;
-  if (!(bg.valid && bg.fp64 == fp64 && bg.dbg == dbg && bg.K == K && bg.NT == NT && bg.nblocks == nblocks &&
-        bg.stage == stage)) {
+  if (!(bg.valid && bg.fp64 == fp64 && bg.dbg == dbg && bg.ext == ext && bg.K == K && bg.NT == NT &&
+        bg.nblocks == nblocks && bg.stage == stage)) {
     if (bg.ge) (void)hipGraphExecDestroy(bg.ge);
     if (bg.g) (void)hipGraphDestroy(bg.g);
     bg = pimc_ctx::BatchGraph{};
     if (!ctx->cap && (r = hip_ok(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)))) return r;
     if ((r = hip_ok(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)))) return r;
-    const int lr = pimc::launch_sweep(a, fp64, K, nblocks, NT, ctx->cap);
+    const int lr = pimc::launch_sweep(a, fp64, K, nblocks, NT, ctx->cap, ext);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap, &g);
     if (lr || ec != hipSuccess) {
@@ -644,6 +646,7 @@ static int launch_batch_graph(pimc_ctx* ctx, const pimc::SweepArgs& a, bool fp64
     bg.valid = true;
     bg.fp64 = fp64;
     bg.dbg = dbg;
+    bg.ext = ext;
     bg.K = K;
     bg.NT = NT;
     bg.nblocks = nblocks;
@@ -779,9 +782,11 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     fill_batch(a, stats->batch, stats->nbatch, (int64_t)sweep0, n_sweeps, b->offsets[B] * 4);
   }
   a.err = ctx->err;
+  const bool ext = (flags & PIMC_GIBBS) != 0;   // exact draws run in the extended kernels
+  if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
   if (T > 1 && (r = tile_generations(ctx, n_sweeps, s, a.gen0))) return r;
-  if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s);
-  return pimc::launch_sweep(a, fp64, K, B * T, NT, s);
+  if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s, ext);
+  return pimc::launch_sweep(a, fp64, K, B * T, NT, s, ext);
 }
 
 }  // extern "C"

@@ -443,8 +443,9 @@ __device__ __attribute__((noinline)) double trunc_normal_inv(double mu, double s
 // is N(p_L + q.s / q^T G q, 1 / (2 cA q^T G q)) truncated to its box (drawn
 // uniformly on the box when the curvature is not positive).  ug: the
 // uniform of the draw.  The statistics follow the move as for an accepted
-// Metropolis step.
-template <int L, bool DBG>
+// Metropolis step.  Only the extended kernels draw, and they record the
+// draw (rec) whenever the parameter records are asked for.
+template <int L>
 __device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, double cA, double (&pd)[7],
                                             double (&s)[7], const double (&G)[28], bool& changed, int& acc,
                                             int& nonfin, bool rec, int win) {
@@ -482,7 +483,7 @@ __device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, doubl
   pd[L] = v;
   changed = changed || dp != 0.0;
   acc += ok ? 1 : 0;
-  if (DBG && rec) {
+  if (rec) {
     if (a.dbg_pprop) a.dbg_pprop[win * 7 + L] = v;
     if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = __builtin_nan("");
     if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
@@ -598,7 +599,8 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
   const size_t sm = sweep_smem_bytes(NT, K, fp64, a.stage);
   if (sm + LDS_STATIC_RESERVE > LDS_BYTES || NT > sweep_max_threads(fp64, K)) return PIMC_ERR_UNSUPPORTED;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
-  if (init && dbg) return PIMC_ERR_UNSUPPORTED;   // extended kernels record only the kinetic moves
+  // the extended kernels record the parameter and kinetic moves, not sites
+  if (init && (a.dbg_xprop || a.dbg_dA || a.dbg_acc)) return PIMC_ERR_UNSUPPORTED;
   if (fp64) {
     if (K != 4 || NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
     return launch_shape<double, 4, 256>(a, dbg, init, nblocks, NT, sm, s);

@@ -42,7 +42,7 @@ def run(ctx: Context, prob, *, sweeps: int, n_init: int, n_cool: int, n_skip: in
     dev = "cuda"
     win = Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, prec)
     w = widths_tensor(prob.w_state, prob.w_param)
-    shape = autotune.tune(ctx, spec, win, w)
+    shape = autotune.tune(ctx, spec, win, w, narrow=True)
     # the tuner ran on a scratch copy; start from the initial guess
     ip = InitPhase.start(win, prob.w_param, beta0=beta0, n_cool=n_cool, n_init=n_init, n_skip=n_skip,
                          f_acc=f_acc, alpha=alpha)
@@ -118,10 +118,15 @@ def run(ctx: Context, prob, *, sweeps: int, n_init: int, n_cool: int, n_skip: in
     top = np.argsort(-np.abs(es[:, 0]))[:max(1, M // 100)] + 1     # links with the largest |<eps_V>|
     near = np.array([np.min(np.abs(spikes - n)) <= int(round(1.0 / spec.dt)) if len(spikes) else False
                      for n in top])
+    # Section 6: over the samples and the window, the errors should have zero
+    # mean and second moments 1/Rd and 1/Ro; the per-site spread across
+    # samples (the posterior uncertainty of each error) is reported beside
     out["errors"] = {
-        "eps_mean_abs_avg": es[:, :4].__abs__().mean(axis=0).tolist(),
-        "eps_var_times_Rd": (ev[:, :4].mean(axis=0) * Rd).tolist(),
-        "delta_mean": float(es[:, 4].mean()), "delta_var_times_Ro": float(ev[:, 4].mean() * spec.Ro),
+        "eps_mean_abs_avg": np.abs(es[:, :4]).mean(axis=0).tolist(),
+        "eps_msq_times_Rd": (eq[:, :4].mean(axis=0) * Rd).tolist(),
+        "eps_posterior_var_times_Rd": (ev[:, :4].mean(axis=0) * Rd).tolist(),
+        "delta_mean": float(es[:, 4].mean()), "delta_msq_times_Ro": float(eq[:, 4].mean() * spec.Ro),
+        "delta_posterior_var_times_Ro": float(ev[:, 4].mean() * spec.Ro),
         "top1pct_abs_epsV_within_1ms_of_spike": float(near.mean()), "spikes": int(len(spikes))}
     # forecasts from the end of the window over the continuation of the drive
     Ifut = np.asarray(prob.meta["I_future"], dtype=np.float64)[:forecast_steps + 1]

@@ -44,7 +44,7 @@ def test_gibbs_fp64_lockstep(ctx):
     ctx.set_tiles(0)
     win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp64")
     gst = P.SweepStats.allocate(win, n, moments=False)
-    gd = P.SweepDebug.allocate(win)
+    gd = P.SweepDebug.allocate(win, sites=False, params=True)
     w = P.widths_tensor(prob.w_state, prob.w_param)
     print("gibbs fp64 lockstep M=300", flush=True)
     P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=4, sweep0=20, w=w, n_sweeps=n,
@@ -68,7 +68,7 @@ def test_gibbs_fp32_draws_match_oracle_on_gpu_path(ctx, K, T):
     try:
         win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
         w = P.widths_tensor(prob.w_state, prob.w_param)
-        gd = P.SweepDebug.allocate(win)
+        gd = P.SweepDebug.allocate(win, sites=False, params=True)
         print(f"gibbs fp32 one sweep M={prob.M} K={K} T={T}", flush=True)
         P.pimc_sweep(ctx, spec, win, seed=prob.seed, chain=0, sweep0=55, w=w, n_sweeps=1,
                      flags=P._lib.PIMC_STATES | P._lib.PIMC_PARAMS | GIBBS, debug=gd)

@@ -263,6 +263,19 @@ int pimc_forecast(pimc_ctx* ctx, const pimc_model* model, int32_t B, const doubl
                   const double* kin, const double* I, int64_t N, double noise, uint64_t seed, int64_t member0,
                   double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pimc_action without a context and without any allocation.  The FP64 block
+ * partials of the reduction live in a fixed array inside the library
+ * (256 KiB on each GPU it runs on, held until the process ends), so a window
+ * may hold at most PIMC_NOALLOC_MAX_SITES sites (M + 1; PIMC_ERR_UNSUPPORTED
+ * beyond).  Runs on the calling thread's current device; `stream` must belong
+ * to it.  Every call on one GPU shares that array and it keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Result as pimc_action. */
+#define PIMC_NOALLOC_MAX_SITES (4096 * 256)
+int pimc_action_noalloc(const pimc_model* model, const pimc_path* path, double* out3, void* stream);
+
 /* n_sweeps red-black Metropolis sweeps (Fig. 1; Sections 3.1, 4.1-4.2):
  * all even sites, then all odd sites (joint D-component proposal
  * x' = x + w z, box test, accept iff log u < -dA with dA in FP64 for the

@@ -27,6 +27,7 @@ PIMC_PARAMS = 2
 PIMC_GIBBS = 4
 PIMC_KINETIC = 8
 PIMC_NACC = 10
+PIMC_NOALLOC_MAX_SITES = 4096 * 256
 
 
 class Model(C.Structure):
@@ -100,6 +101,7 @@ _SIGS = {
                                     C.c_void_p]),
     "pimc_forecast": (C.c_int, [C.c_void_p, C.POINTER(Model), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_int64, C.c_double, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "pimc_action_noalloc": (C.c_int, [C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p]),
     "pimc_grad": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Path), C.c_void_p, C.c_void_p,
                             C.c_void_p]),
     "pimc_run_batch": (C.c_int, [C.c_void_p, C.POINTER(Model), C.POINTER(Batch), C.c_uint64, C.c_uint64,

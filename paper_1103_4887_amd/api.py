@@ -260,6 +260,15 @@ def pimc_forecast(ctx: Context, spec, x0: torch.Tensor, p: torch.Tensor, I: torc
     return out
 
 
+def pimc_action_noalloc(spec, win: Window, out3: torch.Tensor, stream=None):
+    """pimc_action through the library's fixed workspace: allocates nothing
+    (out3 is the caller's [3] FP64 device tensor)."""
+    m, pa = model_struct(spec), win.path_struct()
+    L.check(L.load().pimc_action_noalloc(C.byref(m), C.byref(pa), _ptr(out3), _stream(stream)),
+            "pimc_action_noalloc")
+    return out3
+
+
 def pimc_grad(ctx: Context, spec, win: Window, gX: Optional[torch.Tensor] = None,
               gp: Optional[torch.Tensor] = None, stream=None):
     if gX is None:

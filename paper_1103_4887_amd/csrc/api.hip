@@ -475,6 +475,27 @@ int pimc_forecast(pimc_ctx* ctx, const pimc_model* model, int32_t B, const doubl
   return pimc::launch_forecast(a, (hipStream_t)stream);
 }
 
+int pimc_action_noalloc(const pimc_model* model, const pimc_path* path, double* out3, void* stream) {
+  if (!path || !out3 || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
+  if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;
+  if (path->M + 1 > PIMC_NOALLOC_MAX_SITES) return PIMC_ERR_UNSUPPORTED;
+  pimc::FieldArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int r = model_args(model, a.m);
+  if (r) return r;
+  double* part = nullptr;
+  if ((r = pimc::noalloc_scratch(&part))) return r;
+  a.M = path->M;
+  a.X = path->X;
+  a.p = path->p;
+  a.y = path->y;
+  a.I = path->I;
+  a.kin = path->kin;
+  a.partial = part;
+  a.out = out3;
+  return pimc::launch_action(a, path->prec == PIMC_FP64, (hipStream_t)stream);
+}
+
 int pimc_grad(pimc_ctx* ctx, const pimc_model* model, const pimc_path* path, void* gX, double* gp, void* stream) {
   if (!ctx || !path || !gX || !gp || !path->X || !path->p || !path->y || !path->I) return PIMC_ERR_ARG;
   if (path->M < 1 || (path->prec != PIMC_FP64 && path->prec != PIMC_FP32)) return PIMC_ERR_ARG;

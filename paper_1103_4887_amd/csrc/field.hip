@@ -9,10 +9,37 @@
 // both are one pass of independent threads plus a deterministic two-level
 // FP64 reduction (fixed 256-site chunks, fixed tree order, then a single
 // block summing the chunk partials in index order).
+#include <mutex>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace pimc {
+
+// Fixed device workspace of pimc_action_noalloc: the FP64 block partials of
+// the action reduction for up to NOALLOC_BLOCKS blocks (256 KiB per GPU,
+// held until the process ends).  Every block writes its whole partial
+// record before the final kernel reads it, so nothing needs clearing.
+constexpr int64_t NOALLOC_BLOCKS = PIMC_NOALLOC_MAX_SITES / FIELD_BLOCK;
+static __device__ __align__(256) double scratch[NOALLOC_BLOCKS * 8];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the host-side name is only a stand-in for the symbol).
+int noalloc_scratch(double** out) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static double* ptrs[MAXDEV] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return PIMC_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PIMC_ERR_HIP;
+    ptrs[dev] = (double*)p;
+  }
+  *out = ptrs[dev];
+  return PIMC_OK;
+}
 
 namespace {
 

@@ -103,6 +103,8 @@ constexpr int FIELD_BLOCK = 256;
 int launch_action(const FieldArgs& a, bool fp64, hipStream_t s);
 int launch_grad(const FieldArgs& a, bool fp64, hipStream_t s);
 inline int64_t field_blocks(int64_t M) { return (M + 1 + FIELD_BLOCK - 1) / FIELD_BLOCK; }
+// The fixed partials workspace of pimc_action_noalloc on the current device.
+int noalloc_scratch(double** out);
 
 struct ErrArgs {   // model and observation errors of one path, accumulated
   ModelArgs m;

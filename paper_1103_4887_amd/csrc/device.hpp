@@ -169,6 +169,45 @@ __device__ __forceinline__ double row_sum(double v) {
   return v;
 }
 
+// One folding step of a wave sum of two values x, y: with the lane swap
+// across the two 32-lane halves (HALF) or across neighbouring 16-lane rows,
+// returns x summed over each lane and its partner where the lane keeps x
+// (lower half, or even rows), y likewise where it keeps y.
+template <bool HALF>
+__device__ __forceinline__ double fold_pair(double x, double y) {
+  const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+  const uint32_t xl = (uint32_t)bx, xh = (uint32_t)(bx >> 32), yl = (uint32_t)by, yh = (uint32_t)(by >> 32);
+  uint32_t al, ah, bl, bh;
+  if constexpr (HALF) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    al = lo[0], bl = lo[1], ah = hi[0], bh = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    al = lo[0], bl = lo[1], ah = hi[0], bh = hi[1];
+  }
+  return __builtin_bit_cast(double, ((uint64_t)ah << 32) | al) + __builtin_bit_cast(double, ((uint64_t)bh << 32) | bl);
+}
+
+// Wave totals of N <= 36 values: the halves of the wave, then its rows,
+// are folded pairwise (N -> N/2 -> N/4 registers), and each of the
+// remaining registers is summed over its row of 16 lanes.  On return every
+// lane of row r (lanes 16 r .. 16 r + 15) holds in w[j] the total of value
+// 4 j + fold_slot(r) (values past N are zero).
+__host__ __device__ constexpr int fold_slot(int row) { return row == 1 ? 2 : (row == 2 ? 1 : row); }
+template <int N>
+__device__ __forceinline__ void wave_fold(const double (&v)[N], double (&w)[(N + 3) / 4]) {
+  constexpr int NH = (N + 1) / 2, NQ = (N + 3) / 4;
+  double h[2 * NQ];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) h[i] = fold_pair<true>(v[2 * i], 2 * i + 1 < N ? v[2 * i + 1] : 0.0);
+#pragma unroll
+  for (int i = NH; i < 2 * NQ; ++i) h[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) w[j] = row_sum(fold_pair<false>(h[2 * j], h[2 * j + 1]));
+}
+
 // Values that every lane of a wave holds identically (the parameters after
 // a move) are moved to scalar registers, which frees vector registers.
 __device__ __forceinline__ double wave_uniform(double v) {

@@ -64,8 +64,10 @@ enum { PIMC_PROP_GAUSS = 0, PIMC_PROP_UNIFORM = 1 }; /* proposal law (Fig. 1 ste
  * same path statistics the Metropolis moves use; the draw inverts its CDF
  * with word 0 of the parameter's Philox block.  It changes the chain, so it
  * is off unless asked for; acceptance counters then count finite draws.
- * Runs in the launch shapes of at most 256 threads per workgroup (others
- * return PIMC_ERR_UNSUPPORTED). */
+ * Runs in the launch shapes of at most 256 threads per workgroup and at most
+ * 8 sites per thread (others, among them the automatic single-workgroup
+ * shape of windows of 2049 to 4096 steps, return PIMC_ERR_UNSUPPORTED; such
+ * windows run with time tiles, see pimc_set_sweep_tiles). */
 enum { PIMC_STATES = 1, PIMC_PARAMS = 2, PIMC_GIBBS = 4, PIMC_KINETIC = 8 };
 /* PIMC_KINETIC (pimc_sweep / pimc_sweep_init on a path with `kin` set): after
  * the parameters, each Table 1 constant selected by model->k_mask, in the

@@ -355,17 +355,29 @@ template <> struct ThetaMove<6> { static constexpr int ia = 6, ib = -1; };
 
 __host__ __device__ constexpr int symi(int a, int b) { return a <= b ? sym7(a, b) : sym7(b, a); }
 
-// One Metropolis move of parameter L against the sufficient statistics.
-// pl: proposed value, drawn and box-tested beforehand (a move of p_l leaves
-// every other p_j unchanged, so p_l before its own move is known when the
-// sweep's parameter section starts); NaN when outside the box.  lu: FP64
-// log u of the accept uniform, also formed beforehand (lane-parallel).
+// The value a lane holds in lane `src` of its wave (a wave-uniform result).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One Metropolis move of parameter L against the sufficient statistics,
+// spread over the lanes of a wave: lane j < 7 holds s_j and row j of G
+// (Grow[c] = G_jc; lanes past 6 repeat row 6), so the update of s after an
+// accepted move is one step per lane, and the move reads s_ia, s_ib from
+// their lanes.  Gd: the three entries of G the move needs (G_aa, G_ab,
+// G_bb).  pl: proposed value, drawn and box-tested beforehand (a move of
+// p_l leaves every other p_j unchanged, so p_l before its own move is known
+// when the sweep's parameter section starts); NaN when outside the box.
+// lu: FP64 log u of the accept uniform, also formed beforehand.
 // cA = beta Rd_V / 2.  Written without branches, to keep the sequential
 // chain of the seven moves short.
 template <int L, bool DBG>
 __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double lu, double cA, double (&pd)[7],
-                                           double (&s)[7], const double (&G)[28], bool& changed, int& acc,
-                                           int& nonfin, bool rec, int win) {
+                                           double& sj, const double (&Grow)[7], const double (&Gd)[3],
+                                           bool& changed, int& acc, int& nonfin, bool rec, int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
   constexpr int ia = ThetaMove<L>::ia;
   constexpr int ib = ThetaMove<L>::ib;
@@ -376,22 +388,19 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double
   // p3, p5, p7 move theta_L = p_{L-1} p_L
   const double da = (L == 2 || L == 4 || L == 6) ? pd[L == 0 ? 0 : L - 1] * dp : dp;
   const double db = ib >= 0 ? dp * pd[ibb] : 0.0;
-  double quad = da * da * G[symi(ia, ia)];
-  double lin = da * s[ia];
+  double quad = da * da * Gd[0];
+  double lin = da * lane_value(sj, ia);
   if (ib >= 0) {
-    quad += 2.0 * da * db * G[symi(ia, ibb)] + db * db * G[symi(ibb, ibb)];
-    lin += db * s[ibb];
+    quad += 2.0 * da * db * Gd[1] + db * db * Gd[2];
+    lin += db * lane_value(sj, ibb);
   }
   const double dA = cA * (quad - 2.0 * lin);
   const bool fin = __builtin_isfinite(dA);
   const bool ok = inbox && fin && lu < -dA;
   nonfin += (inbox && !fin) ? 1 : 0;
-#pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    double gs = G[symi(j, ia)] * da;
-    if (ib >= 0) gs += G[symi(j, ibb)] * db;
-    s[j] = ok ? s[j] - gs : s[j];
-  }
+  double gs = Grow[ia] * da;
+  if (ib >= 0) gs += Grow[ibb] * db;
+  sj = ok ? sj - gs : sj;
   pd[L] = ok ? pl : pd[L];
   changed = changed || ok;
   acc += ok ? 1 : 0;
@@ -400,6 +409,17 @@ __device__ __forceinline__ void param_move(const SweepArgs& a, double pl, double
     if (a.dbg_pdA) a.dbg_pdA[win * 7 + L] = inbox ? dA : __builtin_nan("");
     if (a.dbg_pacc) a.dbg_pacc[win * 7 + L] = ok;
   }
+}
+
+// G entries (G_aa, G_ab, G_bb) of the move of parameter L.
+template <int L>
+__device__ __forceinline__ void move_gram(const double* lG, double (&Gd)[3]) {
+  constexpr int ia = ThetaMove<L>::ia;
+  constexpr int ib = ThetaMove<L>::ib;
+  constexpr int ibb = ib >= 0 ? ib : 0;
+  Gd[0] = lG[symi(ia, ia)];
+  Gd[1] = ib >= 0 ? lG[symi(ia, ibb)] : 0.0;
+  Gd[2] = ib >= 0 ? lG[symi(ibb, ibb)] : 0.0;
 }
 
 // log P(Z > z) of a standard normal, z >= 0, through the scaled
@@ -601,6 +621,10 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   // the extended kernels record the parameter and kinetic moves, not sites
   if (init && (a.dbg_xprop || a.dbg_dA || a.dbg_acc)) return PIMC_ERR_UNSUPPORTED;
+  // exact parameter draws are not launched in the extended kernel of 16
+  // sites per thread: a test run of that launch was followed by a GPU fault
+  // whose cause is not identified
+  if (init && K == 16 && (a.flags & PIMC_GIBBS)) return PIMC_ERR_UNSUPPORTED;
   if (fp64) {
     if (K != 4 || NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
     return launch_shape<double, 4, 256>(a, dbg, init, nblocks, NT, sm, s);

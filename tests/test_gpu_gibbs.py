@@ -59,7 +59,12 @@ def test_gibbs_fp64_lockstep(ctx):
     assert (acc[2:9] == n).all()
 
 
-@pytest.mark.parametrize("K,T", [(2, 16), (0, 0)])
+@pytest.mark.parametrize("K,T", [
+    (2, 16),
+    pytest.param(0, 0, marks=pytest.mark.skip(
+        reason="the automatic shape of this window (16 sites x 256 threads, extended kernel) is refused for exact "
+               "draws: a GPU run of this case was followed by a GPU fault whose cause is not identified")),
+])
 def test_gibbs_fp32_draws_match_oracle_on_gpu_path(ctx, K, T):
     prob = W.config_problem("c2", init="guess")
     spec = prob.model
@@ -82,3 +87,20 @@ def test_gibbs_fp32_draws_match_oracle_on_gpu_path(ctx, K, T):
     OG.param_gibbs(spec, Xg, I32, p, 55, prob.seed, 0)
     np.testing.assert_allclose(gd.pprop.cpu().numpy(), p, rtol=1e-9)
     np.testing.assert_allclose(win.p.cpu().numpy(), p, rtol=1e-9)
+
+
+def test_gibbs_refused_at_sixteen_sites_per_thread(ctx):
+    """The single-workgroup shape of 16 sites per thread is refused on the
+    host for exact draws (nothing is launched); time tiles run them."""
+    prob = W.config_problem("c2", init="guess")
+    win = P.Window.from_arrays(prob.X0, prob.p0, prob.y, prob.I, "fp32")
+    w = P.widths_tensor(prob.w_state, prob.w_param)
+    X0 = win.X.clone()
+    ctx.set_tile(0)
+    ctx.set_tiles(0)
+    with pytest.raises(P._lib.PimcError) as e:
+        P.pimc_sweep(ctx, prob.model, win, seed=prob.seed, chain=0, sweep0=1, w=w, n_sweeps=1,
+                     flags=P._lib.PIMC_STATES | P._lib.PIMC_PARAMS | GIBBS)
+    assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
+    assert ctx.sync() == 0
+    assert torch.equal(win.X, X0)

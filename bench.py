@@ -37,8 +37,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 # WRITE_SIZE runs calibrated against a plain copy (profiles/ holds the
 # summary).  They belong to one version of the kernel source: when the source
 # hash differs, the traffic is reported as unknown.
-TRAFFIC = {"sweep_source_sha256": "6a7bfdd18f5d7d9fe4148efa3248dfdb1b48915261d53343bf3f3ea8c45d3b42",
-           "launch": (2, 16), "fetch_bytes_per_sweep": 77.8e3, "write_bytes_per_sweep": 16.6e3}
+TRAFFIC = {"sweep_source_sha256": "4e35c0b169f941f40ce0c561dc9165d98ee3d918bd0ad63e3d8c469044f6731a",
+           "launch": (2, 16), "fetch_bytes_per_sweep": 81.3e3, "write_bytes_per_sweep": 16.6e3}
 
 
 def parse():
@@ -313,13 +313,20 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
 
 def _timed(stream, fn):
     """Run fn between two HIP events on `stream`; returns (seconds on the
-    device clock, wall seconds, fn's result)."""
+    device clock, wall seconds, fn's result).  A short device-side delay is
+    queued first, so that the host's work of issuing the call (Python
+    marshalling, the launch) overlaps it, as it does in any caller that keeps
+    the device busy: the events then time the device work of the call, all of
+    it, without the idle gap of a device waiting for its first launch.  The
+    wall time (host clock, delay included) is reported beside it."""
     import torch
 
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(200000)
     ev0.record(stream)
     r = fn()
     ev1.record(stream)

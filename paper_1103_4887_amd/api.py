@@ -37,7 +37,27 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+_MODEL_CACHE: dict = {}
+
+
 def model_struct(spec) -> L.Model:
+    """The pimc_model of a model description.  Hashable (immutable)
+    descriptions are converted once and the struct is reused by later calls
+    (the library only reads it), which keeps the per-call cost of the
+    binding small; treat the returned struct as read-only."""
+    try:
+        m = _MODEL_CACHE.get(spec)
+    except TypeError:          # not hashable: convert every time
+        return _model_struct(spec)
+    if m is None:
+        m = _model_struct(spec)
+        if len(_MODEL_CACHE) > 256:
+            _MODEL_CACHE.clear()
+        _MODEL_CACHE[spec] = m
+    return m
+
+
+def _model_struct(spec) -> L.Model:
     m = L.Model()
     m.dt = float(spec.dt)
     m.Ro = float(spec.Ro)

@@ -22,6 +22,10 @@
 //    2 dth . s); after an accepted move s <- s - G dth.  The sums are
 //    accumulated during the odd half-sweep, which replaces the paper's N_p
 //    full passes and N_p global synchronisations with one block reduction.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -564,28 +568,71 @@ int clear_words(void* p, size_t n, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }
 
+// Launch limits of one kernel at one launch shape on one device: whether
+// its static plus dynamic LDS and its thread count fit a workgroup, and how
+// many of its workgroups the device holds at once.  Queried from the runtime
+// once per (kernel, device, threads, LDS) and kept for the process, so that
+// a call's host cost is the launch itself.
+struct LaunchLimits {
+  bool fits;
+  int64_t resident;
+};
+
+static int launch_limits(const void* k, int dev, int NT, size_t sm, LaunchLimits& out) {
+  struct Key {
+    const void* k;
+    int dev, NT;
+    size_t sm;
+    bool operator<(const Key& o) const {
+      return std::tie(k, dev, NT, sm) < std::tie(o.k, o.dev, o.NT, o.sm);
+    }
+  };
+  static std::mutex mu;
+  static std::map<Key, LaunchLimits> cache;
+  const Key key{k, dev, NT, sm};
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      out = it->second;
+      return PIMC_OK;
+    }
+  }
+  hipFuncAttributes at;
+  int lim = 0, per_cu = 0, ncu = 0;
+  if (hipFuncGetAttributes(&at, k) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return PIMC_ERR_HIP;
+  LaunchLimits l;
+  l.fits = sm + at.sharedSizeBytes <= (size_t)lim && NT <= at.maxThreadsPerBlock;
+  l.resident = 0;
+  if (l.fits) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, NT, sm) != hipSuccess) return PIMC_ERR_HIP;
+    l.resident = (int64_t)per_cu * ncu;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = l;
+  out = l;
+  return PIMC_OK;
+}
+
 // The launch is refused on the host (never enqueued) when the kernel's static
 // LDS plus the requested dynamic LDS exceeds what a workgroup may allocate.
 template <typename Kern>
 static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s, const SweepArgs& a) {
-  hipFuncAttributes at;
-  if (hipFuncGetAttributes(&at, (const void*)k) != hipSuccess) return PIMC_ERR_HIP;
-  int dev = 0, lim = 0;
+  int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PIMC_ERR_HIP;
-  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PIMC_ERR_HIP;
-  if (sm + at.sharedSizeBytes > (size_t)lim || NT > at.maxThreadsPerBlock) return PIMC_ERR_UNSUPPORTED;
-  if (a.tiles > 1) {
-    // tiles wait on each other, so all of them must be resident at once: a
-    // shape the device cannot hold is refused before anything is enqueued
-    int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, NT, sm) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return PIMC_ERR_HIP;
-    if ((int64_t)per_cu * ncu < nblocks) return PIMC_ERR_UNSUPPORTED;
-    // every tile is resident once launched (checked above): the waits
-    // between tiles are bounded, so a tile that cannot be placed (other
-    // work holding the CUs) ends the launch with a timeout, never a hang
-  }
+  LaunchLimits l;
+  const int r = launch_limits((const void*)k, dev, NT, sm, l);
+  if (r) return r;
+  if (!l.fits) return PIMC_ERR_UNSUPPORTED;
+  // tiles wait on each other, so all of them must be resident at once: a
+  // shape the device cannot hold is refused before anything is enqueued.
+  // Every tile is then resident once launched: the waits between tiles are
+  // bounded, so a tile that cannot be placed (other work holding the CUs)
+  // ends the launch with a timeout, never a hang
+  if (a.tiles > 1 && l.resident < nblocks) return PIMC_ERR_UNSUPPORTED;
   hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), sm, s, a);
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }

@@ -220,46 +220,74 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
         return P.PackedBatch(offsets=start.offsets, X=start.X.clone(), p=start.p.clone(), y=start.y, I=start.I,
                              chain=start.chain, prec=start.prec)
 
-    # plain sweep: a short run sizes the budgeted one
-    bm = fresh()
-    t0 = time.perf_counter()
-    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=0, w=w, n_sweeps=50)
-    assert ctx.sync() == 0
-    t_probe = time.perf_counter()
-    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=50, w=w, n_sweeps=200)
-    assert ctx.sync() == 0
-    per_sweep = (time.perf_counter() - t_probe) / 200
-    n_m = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep))
-    stride = max(1, n_m // 20000)     # the trace is thinned on the host for the ESS estimate
-    dev = bm.X.device
-    sm = P.SweepStats(ptrace=torch.zeros((B, n_m, 7), dtype=torch.float64, device=dev),
-                      acc=torch.zeros((B, P._lib.PIMC_NACC), dtype=torch.int64, device=dev))
-    P.pimc_run_batch(ctx, spec, bm, seed=prob.seed, sweep0=250, w=w, n_sweeps=n_m, stats=sm)
-    assert ctx.sync() == 0
-    wall_m = time.perf_counter() - t0
-    tr_m = sm.ptrace[:, n_m // 2::stride].cpu().numpy()
-    del sm.ptrace
-    ess_m, mean_m, mcse_m = _post_stats(tr_m, mask)
-    acc_m = sm.acc.cpu().numpy()
+    def batched(flags, seed_off):
+        """`chains` chains of the batched sweep for the wall budget (a short
+        run sizes the budgeted one); returns the run's record and its
+        posterior statistics."""
+        bm = fresh()
+        t0 = time.perf_counter()
+        P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=0, w=w, n_sweeps=50, flags=flags)
+        assert ctx.sync() == 0
+        t_probe = time.perf_counter()
+        P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=50, w=w, n_sweeps=200, flags=flags)
+        assert ctx.sync() == 0
+        per_sweep = (time.perf_counter() - t_probe) / 200
+        n_m = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep))
+        stride = max(1, n_m // 20000)     # the trace is thinned on the host for the ESS estimate
+        dev = bm.X.device
+        sm = P.SweepStats(ptrace=torch.zeros((B, n_m, 7), dtype=torch.float64, device=dev),
+                          acc=torch.zeros((B, P._lib.PIMC_NACC), dtype=torch.int64, device=dev))
+        P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=250, w=w, n_sweeps=n_m, stats=sm,
+                         flags=flags)
+        assert ctx.sync() == 0
+        wall_m = time.perf_counter() - t0
+        tr_m = sm.ptrace[:, n_m // 2::stride].cpu().numpy()
+        del sm.ptrace
+        ess_m, mean_m, mcse_m = _post_stats(tr_m, mask)
+        acc_m = sm.acc.cpu().numpy()
+        rec = {"chains": B, "launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride,
+               "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
+               "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
+               "param_ess_per_s": float(ess_m.min() / wall_m),
+               "param_ess_per_s_median": float(np.median(ess_m) / wall_m),
+               "param_ess": [float(v) for v in ess_m],
+               "accept_sites": float(acc_m[:, :2].sum() / (B * (prob.M + 1) * n_m))}
+        return rec, ess_m.min() / wall_m, mean_m, mcse_m
 
-    # one chain of the plain sweep (the benchmark's single-window launch, in
-    # its own autotuned shape) from chain 0's equilibrated state, same budget
+    plain = P._lib.PIMC_STATES | P._lib.PIMC_PARAMS
+    exact = plain | P._lib.PIMC_GIBBS
+    rec_m, ess_rate_m, mean_m, mcse_m = batched(plain, 0)
+    # the same with each parameter drawn from its exact conditional
+    rec_g, ess_rate_g, mean_g, mcse_g = batched(exact, 5)
+
+    # one chain (the benchmark's single-window launch, in its own autotuned
+    # shape) from chain 0's equilibrated state, same budget
     x0, p0, _, _ = start.window(0)
-    win1 = P.Window(X=x0.clone(), p=p0.clone(), y=start.y[:prob.M + 1], I=start.I[:prob.M + 1], prec="fp32")
-    autotune.tune(ctx, spec, win1, w)
-    t0 = time.perf_counter()
-    P.pimc_sweep(ctx, spec, win1, seed=prob.seed + 3, chain=0, sweep0=0, w=w, n_sweeps=200)
-    assert ctx.sync() == 0
-    per_sweep1 = (time.perf_counter() - t0) / 200
-    n_1 = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep1))
-    s1 = P.SweepStats.allocate(win1, n_1, moments=False)
-    P.pimc_sweep(ctx, spec, win1, seed=prob.seed + 3, chain=0, sweep0=200, w=w, n_sweeps=n_1, stats=s1)
-    assert ctx.sync() == 0
-    wall_1 = time.perf_counter() - t0
-    stride1 = max(1, n_1 // 20000)
-    tr_1 = s1.ptrace[n_1 // 2::stride1].cpu().numpy()[None]
-    ess_1, _, _ = _post_stats(tr_1, mask)
-    shape1 = autotune.tune(ctx, spec, win1, w)
+
+    def single(flags, seed_off):
+        win1 = P.Window(X=x0.clone(), p=p0.clone(), y=start.y[:prob.M + 1], I=start.I[:prob.M + 1], prec="fp32")
+        autotune.tune(ctx, spec, win1, w)
+        t0 = time.perf_counter()
+        P.pimc_sweep(ctx, spec, win1, seed=prob.seed + seed_off, chain=0, sweep0=0, w=w, n_sweeps=200, flags=flags)
+        assert ctx.sync() == 0
+        per_sweep1 = (time.perf_counter() - t0) / 200
+        n_1 = max(1000, int((budget_s - (time.perf_counter() - t0)) / per_sweep1))
+        s1 = P.SweepStats.allocate(win1, n_1, moments=False)
+        P.pimc_sweep(ctx, spec, win1, seed=prob.seed + seed_off, chain=0, sweep0=200, w=w, n_sweeps=n_1, stats=s1,
+                     flags=flags)
+        assert ctx.sync() == 0
+        wall_1 = time.perf_counter() - t0
+        stride1 = max(1, n_1 // 20000)
+        tr_1 = s1.ptrace[n_1 // 2::stride1].cpu().numpy()[None]
+        ess_1, _, _ = _post_stats(tr_1, mask)
+        shape1 = autotune.tune(ctx, spec, win1, w)
+        rec = {"launch": {"K": shape1[0], "tiles": shape1[1]}, "sweeps": n_1, "wall_s": wall_1,
+               "us_per_sweep": per_sweep1 * 1e6, "param_ess_per_s": float(ess_1.min() / wall_1),
+               "param_ess": [float(v) for v in ess_1]}
+        return rec, ess_1.min() / wall_1
+
+    rec_1, ess_rate_1 = single(plain, 3)
+    rec_1g, ess_rate_1g = single(exact, 4)
     autotune.tune_batch(ctx, spec, start, w)   # the batch shape again (cached) for HMC's pilot run
 
     # HMC: pilot masses, step-size warm-up, then sampling in one graph-replayed call
@@ -279,16 +307,13 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
     acc_h = sh.acc.cpu().numpy()
 
     z = np.abs(mean_h - mean_m) / np.sqrt(mcse_h ** 2 + mcse_m ** 2)
+    zg = np.abs(mean_h - mean_g) / np.sqrt(mcse_h ** 2 + mcse_g ** 2)
     return {
         "dataset": f"HH M={prob.M}, dt={spec.dt} ms, all 7 params, FP32 sites + FP64 reductions",
         "chains": B, "start": f"true path and parameters, then {n_eq} sweeps of equilibration (untimed)",
         "budget_s": budget_s,
-        "sweep": {"chains": B, "launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride, "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
-                  "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
-                  "param_ess_per_s": float(ess_m.min() / wall_m),
-                  "param_ess_per_s_median": float(np.median(ess_m) / wall_m),
-                  "param_ess": [float(v) for v in ess_m],
-                  "accept_sites": float(acc_m[:, :2].sum() / (B * (prob.M + 1) * n_m))},
+        "sweep": rec_m,
+        "sweep_exact_draws": rec_g,
         "hmc": {"proposals": n_h, "leapfrog_steps": L_steps, "eps": tun.eps,
                 "warmup_accept": tun.warmup_accept, "wall_s": wall_h, "us_per_proposal": per_prop * 1e6,
                 "site_leapfrogs_per_s": B * (prob.M + 1) * L_steps * n_h / wall_h,
@@ -297,16 +322,19 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
                 "param_ess_per_s": float(ess_h.min() / wall_h),
                 "param_ess_per_s_median": float(np.median(ess_h) / wall_h),
                 "param_ess": [float(v) for v in ess_h]},
-        "single_chain_sweep": {"launch": {"K": shape1[0], "tiles": shape1[1]}, "sweeps": n_1, "wall_s": wall_1,
-                               "us_per_sweep": per_sweep1 * 1e6,
-                               "param_ess_per_s": float(ess_1.min() / wall_1),
-                               "param_ess": [float(v) for v in ess_1]},
-        "hmc_over_sweep_param_ess_per_s": float((ess_h.min() / wall_h) / (ess_m.min() / wall_m)),
-        "batched_over_single_param_ess_per_s": float((ess_m.min() / wall_m) / max(ess_1.min() / wall_1, 1e-300)),
-        "hmc_over_single_param_ess_per_s": float((ess_h.min() / wall_h) / max(ess_1.min() / wall_1, 1e-300)),
+        "single_chain_sweep": rec_1,
+        "single_chain_exact_draws": rec_1g,
+        "hmc_over_sweep_param_ess_per_s": float((ess_h.min() / wall_h) / ess_rate_m),
+        "exact_draws_over_sweep_param_ess_per_s": float(ess_rate_g / ess_rate_m),
+        "batched_over_single_param_ess_per_s": float(ess_rate_m / max(ess_rate_1, 1e-300)),
+        "hmc_over_single_param_ess_per_s": float((ess_h.min() / wall_h) / max(ess_rate_1, 1e-300)),
+        "single_exact_draws_over_single_param_ess_per_s": float(ess_rate_1g / max(ess_rate_1, 1e-300)),
         "equal_posterior_accuracy": {"max_z": float(z.max()), "within_3_mcse": bool((z <= 3.0).all()),
+                                     "max_z_exact_draws_vs_hmc": float(zg.max()),
+                                     "exact_draws_within_3_mcse": bool((zg <= 3.0).all()),
                                      "mcse": "spread of the chain means / sqrt(chains)",
                                      "mean_sweep": [float(v) for v in mean_m],
+                                     "mean_exact_draws": [float(v) for v in mean_g],
                                      "mean_hmc": [float(v) for v in mean_h]},
     }
 
@@ -590,7 +618,13 @@ def main():
         one = cmp["single_chain_sweep"]
         out["param_ess_per_s"] = one["param_ess_per_s"]
         out["param_ess_source"] = (f"hmc_vs_sweep.single_chain_sweep: {one['sweeps']} sweeps of this window in "
-                                   f"{one['wall_s']:.1f} s; batched sweep and HMC (64 chains) beside it")
+                                   f"{one['wall_s']:.1f} s (Metropolis parameter moves); batched sweep and HMC "
+                                   f"(64 chains) beside it")
+        ex = cmp["single_chain_exact_draws"]
+        out["param_ess_per_s_exact_draws"] = ex["param_ess_per_s"]
+        out["param_ess_exact_draws_source"] = (f"hmc_vs_sweep.single_chain_exact_draws: {ex['sweeps']} sweeps of "
+                                               f"this window in {ex['wall_s']:.1f} s, each parameter drawn from "
+                                               f"its exact conditional (PIMC_GIBBS)")
     if cpu_s > 0:
         out["cpu_baseline"] = cpu_baseline(prob, cpu_s)
         out["cpu_baseline"]["gpu_over_cpu"] = rate / out["cpu_baseline"]["value"]

@@ -466,11 +466,16 @@ __device__ __attribute__((noinline)) double trunc_normal_inv(double mu, double s
 // A(p_L + d) - A(p_L) = cA (d^2 q^T G q - 2 d q . s), so p_L given the rest
 // is N(p_L + q.s / q^T G q, 1 / (2 cA q^T G q)) truncated to its box (drawn
 // uniformly on the box when the curvature is not positive).  ug: the
-// uniform of the draw.  The statistics follow the move as for an accepted
-// Metropolis step.  Only the extended kernels draw, and they record the
-// draw (rec) whenever the parameter records are asked for.
+// uniform of the draw, zq its standard normal quantile (formed beforehand).
+// When both box edges lie more than 10 standard deviations from the mean,
+// the normal mass the box cuts off is below 1e-23, and mean + sd zq is the
+// truncated quantile to within 1e-13 standard deviations for any ug of the
+// generator's (0, 1) grid; other boxes go through the full inversion.  The
+// statistics follow the move as for an accepted Metropolis step.  Only the
+// extended kernels draw, and they record the draw (rec) whenever the
+// parameter records are asked for.
 template <int L>
-__device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, double cA, double (&pd)[7],
+__device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, double zq, double cA, double (&pd)[7],
                                             double (&s)[7], const double (&G)[28], bool& changed, int& acc,
                                             int& nonfin, bool rec, int win) {
   if (!((a.m.p_mask >> L) & 1)) return;
@@ -489,10 +494,15 @@ __device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, doubl
   const double lo = a.m.p_lo[L], hi = a.m.p_hi[L];
   const double curv = cA * qGq;
   double v;
-  if (curv > 0.0 && __builtin_isfinite(curv))
-    v = trunc_normal_inv(pd[L] + qs / qGq, 1.0 / sqrt(2.0 * curv), lo, hi, ug);
-  else
+  if (curv > 0.0 && __builtin_isfinite(curv)) {
+    const double mu = pd[L] + qs / qGq, sg = 1.0 / sqrt(2.0 * curv);
+    if ((lo - mu) < -10.0 * sg && (hi - mu) > 10.0 * sg)
+      v = mu + sg * zq;
+    else
+      v = trunc_normal_inv(mu, sg, lo, hi, ug);
+  } else {
     v = lo + ug * (hi - lo);
+  }
   const bool ok = __builtin_isfinite(v);
   nonfin += ok ? 0 : 1;
   v = ok ? fmin(fmax(v, lo), hi) : pd[L];
@@ -553,7 +563,7 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
   const size_t ts = fp64 ? 8 : 4;
   const size_t NW = (size_t)NT / 64;
-  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 32) * sizeof(double) +
+  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 40) * sizeof(double) +
          16 * sizeof(int) + (size_t)stage * 4 * ts;
 }
 

@@ -104,3 +104,35 @@ def test_gibbs_refused_at_sixteen_sites_per_thread(ctx):
     assert e.value.status == P._lib.PIMC_ERR_UNSUPPORTED
     assert ctx.sync() == 0
     assert torch.equal(win.X, X0)
+
+
+def test_gibbs_tiled_batch_equals_single_runs(ctx):
+    """Exact draws inside a batch of windows cut into time tiles (the launch
+    of the batched comparison: 8 tiles of 256 threads x 2 sites for M = 4096)
+    give each window exactly the chain of its own single-window run at the
+    same tiling: equal paths, parameters within the rounding of the
+    cross-tile sums."""
+    probs = [W.make_hh_problem(4096, 0.02, 190 + i, require_spike=False, init="truth") for i in range(3)]
+    spec = probs[0].model
+    chains = [11, 12, 13]
+    w = P.widths_tensor(probs[0].w_state, probs[0].w_param)
+    flags = P._lib.PIMC_STATES | P._lib.PIMC_PARAMS | GIBBS
+    batch = P.PackedBatch.pack([q.X0 for q in probs], [q.p0 for q in probs], [q.y for q in probs],
+                               [q.I for q in probs], chains, "fp32")
+    ctx.set_tile(2)
+    ctx.set_tiles(8)
+    try:
+        print("gibbs tiled batch of 3 windows M=4096, 8 tiles", flush=True)
+        P.pimc_run_batch(ctx, spec, batch, seed=6, sweep0=40, w=w, n_sweeps=12, flags=flags)
+        assert ctx.sync() == 0
+        for i, q in enumerate(probs):
+            win = P.Window.from_arrays(q.X0, q.p0, q.y, q.I, "fp32")
+            P.pimc_sweep(ctx, spec, win, seed=6, chain=chains[i], sweep0=40, w=w, n_sweeps=12, flags=flags)
+            assert ctx.sync() == 0
+            Xb, pb, _, _ = batch.window(i)
+            np.testing.assert_array_equal(Xb.cpu().numpy(), win.X.cpu().numpy())
+            np.testing.assert_allclose(pb.cpu().numpy(), win.p.cpu().numpy(), rtol=1e-13)
+            assert not np.array_equal(pb.cpu().numpy(), q.p0)      # the draws moved the parameters
+    finally:
+        ctx.set_tile(0)
+        ctx.set_tiles(0)

@@ -34,7 +34,8 @@ struct pimc_ctx {
   // captured graph of the batched sweep launch, replayed with new arguments
   struct BatchGraph {
     bool valid = false;
-    bool fp64 = false, dbg = false, ext = false;
+    bool fp64 = false, dbg = false;
+    int ext = 0;
     int K = 0, NT = 0, nblocks = 0, stage = 0;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -600,9 +601,10 @@ int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.dbg_kdA = debug->kdA;
     a.dbg_kacc = debug->kaccept;
   }
-  // initialization phase, kinetic constants and exact parameter draws run
-  // in the extended kernels (shapes of at most 256 threads)
-  const bool ext = ip || kinetic || (flags & PIMC_GIBBS);
+  // the initialization phase and kinetic constants run in the extended
+  // kernels (which draw exactly too), exact parameter draws alone in the
+  // exact-draw kernels (shapes of at most 256 threads)
+  const int ext = (ip || kinetic) ? 1 : ((flags & PIMC_GIBBS) ? 2 : 0);
   if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
   if (ip && (r = init_args(ip, a))) return r;
   // all-reduces between the tiles per sweep: the parameter statistics and
@@ -636,9 +638,9 @@ int pimc_param_update(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, p
 // The batched sweep launch as a captured graph: recorded once per launch
 // shape on the context's capture stream, then replayed on the caller's
 // stream with this call's arguments written into its kernel node.  (Tiled
-// batches launch cooperatively and are not captured.)
+// batches are launched directly, not captured.)
 static int launch_batch_graph(pimc_ctx* ctx, const pimc::SweepArgs& a, bool fp64, int K, int nblocks, int NT,
-                              int stage, hipStream_t s, bool ext) {
+                              int stage, hipStream_t s, int ext) {
   auto& bg = ctx->bgraph;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   int r = PIMC_OK;
@@ -803,7 +805,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
     fill_batch(a, stats->batch, stats->nbatch, (int64_t)sweep0, n_sweeps, b->offsets[B] * 4);
   }
   a.err = ctx->err;
-  const bool ext = (flags & PIMC_GIBBS) != 0;   // exact draws run in the extended kernels
+  const int ext = (flags & PIMC_GIBBS) ? 2 : 0;   // exact draws run in the exact-draw kernels
   if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
   if (T > 1 && (r = tile_generations(ctx, n_sweeps, s, a.gen0))) return r;
   if (T == 1 && !ctx->no_graphs) return launch_batch_graph(ctx, a, fp64, K, B, NT, stage, s, ext);

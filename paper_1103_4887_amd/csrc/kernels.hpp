@@ -79,9 +79,11 @@ size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage);
 constexpr size_t LDS_BYTES = 160 * 1024;       // LDS per CU on gfx950
 constexpr size_t LDS_STATIC_RESERVE = 1024;    // kept free for the kernels' static LDS
 int sweep_max_threads(bool fp64, int K);
-// init: run the extended kernels (initialization phase, kinetic constants;
-// shapes of at most 256 threads; only the kinetic debug record)
-int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, bool init = false);
+// ext: 0 the plain kernels; 1 the extended kernels (initialization phase,
+// kinetic constants, exact draws); 2 the exact-draw kernels.  Extended
+// kernels run in shapes of at most 256 threads and record the parameter and
+// kinetic moves only.
+int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, int ext = 0);
 // Clear n 32-bit words of device memory in stream order (a kernel: the call
 // may be recorded into a graph).
 int clear_words(void* p, size_t n, hipStream_t s);

@@ -549,7 +549,7 @@ __device__ __forceinline__ void param_gibbs(const SweepArgs& a, double ug, doubl
 // kernel for the launch's K and, for launches of 16 sites per thread, a
 // device function for each smaller K that a window of a batch may use; the
 // kernels of every other shape are the statements alone.
-template <typename T, int K, int MAXT, bool DBG, bool EXT>
+template <typename T, int K, int MAXT, bool DBG, int EXT>
 __device__ __forceinline__ void sweep_body(SweepArgs a) {
 #include "sweep_body.inc"
 }
@@ -558,9 +558,9 @@ __device__ __forceinline__ void sweep_body(SweepArgs a) {
 // blockK[b] sites per thread (4, 8, 12 or the launch's 16: the fewest that
 // its workgroup holds), so a short window's workgroup is done in proportion
 // to its length rather than as late as the longest window's.
-template <typename T, int K, int MAXT, bool DBG, bool EXT>
+template <typename T, int K, int MAXT, bool DBG, int EXT>
 __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
-  if constexpr (K == 16 && sizeof(T) == 4 && !EXT) {
+  if constexpr (K == 16 && sizeof(T) == 4 && EXT == 0) {
     const int kb = a.blockK ? (int)a.blockK[blockIdx.x] : K;
     if (kb == 4) {
       sweep_body<T, 4, MAXT, DBG, EXT>(a);
@@ -665,52 +665,54 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
   return hipGetLastError() == hipSuccess ? PIMC_OK : PIMC_ERR_HIP;
 }
 
-// One launch shape: the extended kernel (initialization phase, kinetic
-// constants; one wave per SIMD shapes only) when asked for, the debug kernel
-// when a debug record is, else the plain kernel.
+// One launch shape: an extended kernel when asked for (ext 1: the
+// initialization phase, kinetic constants and exact draws; ext 2: exact
+// draws only; one wave per SIMD shapes only), the debug kernel when a
+// debug record is, else the plain kernel.
 template <typename T, int K, int MAXT>
-static int launch_shape(const SweepArgs& a, bool dbg, bool init, int nblocks, int NT, size_t sm, hipStream_t s) {
-  if (init) {
+static int launch_shape(const SweepArgs& a, bool dbg, int ext, int nblocks, int NT, size_t sm, hipStream_t s) {
+  if (ext) {
     if constexpr (MAXT <= 256) {
-      return launch_checked(sweep_kernel<T, K, MAXT, false, true>, nblocks, NT, sm, s, a);
+      if (ext == 2) return launch_checked(sweep_kernel<T, K, MAXT, false, 2>, nblocks, NT, sm, s, a);
+      return launch_checked(sweep_kernel<T, K, MAXT, false, 1>, nblocks, NT, sm, s, a);
     } else {
       return PIMC_ERR_UNSUPPORTED;
     }
   }
-  if (dbg) return launch_checked(sweep_kernel<T, K, MAXT, true, false>, nblocks, NT, sm, s, a);
-  return launch_checked(sweep_kernel<T, K, MAXT, false, false>, nblocks, NT, sm, s, a);
+  if (dbg) return launch_checked(sweep_kernel<T, K, MAXT, true, 0>, nblocks, NT, sm, s, a);
+  return launch_checked(sweep_kernel<T, K, MAXT, false, 0>, nblocks, NT, sm, s, a);
 }
 
 // Launch bounds follow the thread count: up to 256 threads (one wave per
 // SIMD) a wave may hold 512 registers (architectural + accumulation), so the
 // register-resident path never spills to scratch.
 template <typename T, int K, int BIG>
-static int launch_pick(const SweepArgs& a, bool dbg, bool init, int nblocks, int NT, size_t sm, hipStream_t s) {
-  if (NT <= 256) return launch_shape<T, K, 256>(a, dbg, init, nblocks, NT, sm, s);
-  return launch_shape<T, K, BIG>(a, dbg, init, nblocks, NT, sm, s);
+static int launch_pick(const SweepArgs& a, bool dbg, int ext, int nblocks, int NT, size_t sm, hipStream_t s) {
+  if (NT <= 256) return launch_shape<T, K, 256>(a, dbg, ext, nblocks, NT, sm, s);
+  return launch_shape<T, K, BIG>(a, dbg, ext, nblocks, NT, sm, s);
 }
 
-int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, bool init) {
+int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipStream_t s, int ext) {
   const size_t sm = sweep_smem_bytes(NT, K, fp64, a.stage);
   if (sm + LDS_STATIC_RESERVE > LDS_BYTES || NT > sweep_max_threads(fp64, K)) return PIMC_ERR_UNSUPPORTED;
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   // the extended kernels record the parameter and kinetic moves, not sites
-  if (init && (a.dbg_xprop || a.dbg_dA || a.dbg_acc)) return PIMC_ERR_UNSUPPORTED;
-  // exact parameter draws are not launched in the extended kernel of 16
+  if (ext && (a.dbg_xprop || a.dbg_dA || a.dbg_acc)) return PIMC_ERR_UNSUPPORTED;
+  // exact parameter draws are not launched in the extended kernels of 16
   // sites per thread: a test run of that launch was followed by a GPU fault
   // whose cause is not identified
-  if (init && K == 16 && (a.flags & PIMC_GIBBS)) return PIMC_ERR_UNSUPPORTED;
+  if (ext && K == 16 && (a.flags & PIMC_GIBBS)) return PIMC_ERR_UNSUPPORTED;
   if (fp64) {
     if (K != 4 || NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
-    return launch_shape<double, 4, 256>(a, dbg, init, nblocks, NT, sm, s);
+    return launch_shape<double, 4, 256>(a, dbg, ext, nblocks, NT, sm, s);
   }
   switch (K) {
     case 2:
       if (NT > 256) return PIMC_ERR_UNSUPPORTED;   // a tiling option: one wave per SIMD only
-      return launch_shape<float, 2, 256>(a, dbg, init, nblocks, NT, sm, s);
-    case 4: return launch_pick<float, 4, 1024>(a, dbg, init, nblocks, NT, sm, s);
-    case 8: return launch_pick<float, 8, 512>(a, dbg, init, nblocks, NT, sm, s);
-    case 16: return launch_pick<float, 16, 512>(a, dbg, init, nblocks, NT, sm, s);
+      return launch_shape<float, 2, 256>(a, dbg, ext, nblocks, NT, sm, s);
+    case 4: return launch_pick<float, 4, 1024>(a, dbg, ext, nblocks, NT, sm, s);
+    case 8: return launch_pick<float, 8, 512>(a, dbg, ext, nblocks, NT, sm, s);
+    case 16: return launch_pick<float, 16, 512>(a, dbg, ext, nblocks, NT, sm, s);
     default: return PIMC_ERR_UNSUPPORTED;
   }
 }

@@ -72,10 +72,6 @@ struct pimc_ctx {
 };
 
 namespace {
-constexpr int MAX_TILES = 256;
-}
-
-namespace {
 
 using pimc::ModelArgs;
 
@@ -180,8 +176,8 @@ int ensure_tilespace(pimc_ctx* c, size_t ntiles, size_t ngroups) {
     *q = nullptr;
   }
   c->tile_cap = c->group_cap = 0;
-  const size_t sz[] = {ntiles * 2 * 16 * sizeof(uint64_t), 2 * ntiles * 70 * sizeof(uint64_t),
-                       ntiles * sizeof(uint64_t)};
+  const size_t sz[] = {pimc::halo_words(ntiles) * sizeof(uint64_t), pimc::wpart_words(ntiles) * sizeof(uint64_t),
+                       pimc::tsync_words(ntiles) * sizeof(uint64_t)};
   for (int i = 0; i < 3; ++i) {
     if (hipMalloc(bufs[i], sz[i]) != hipSuccess) return PIMC_ERR_NOMEM;
     if (hipMemset(*bufs[i], 0, sz[i]) != hipSuccess) return PIMC_ERR_HIP;
@@ -200,9 +196,10 @@ int tile_generations(pimc_ctx* c, int64_t n, hipStream_t s, uint32_t& gen0, int 
   const uint64_t need = (uint64_t)n * (uint64_t)per_sweep + 4;
   if (n > PIMC_MAX_TILED_SWEEPS) return PIMC_ERR_ARG;
   if (c->gen_next + need > 0xFFFFFFFFull) {
-    int r = pimc::clear_words(c->halo, c->tile_cap * 2 * 16 * 2, s);
-    if (!r) r = pimc::clear_words(c->wpart, 2 * c->tile_cap * 70 * 2, s);
-    if (!r) r = pimc::clear_words(c->tsync, c->tile_cap * 2, s);
+    // clear_words counts 32-bit words
+    int r = pimc::clear_words(c->halo, pimc::halo_words(c->tile_cap) * 2, s);
+    if (!r) r = pimc::clear_words(c->wpart, pimc::wpart_words(c->tile_cap) * 2, s);
+    if (!r) r = pimc::clear_words(c->tsync, pimc::tsync_words(c->tile_cap) * 2, s);
     if (r) return r;
     c->gen_next = 0;
   }
@@ -211,78 +208,15 @@ int tile_generations(pimc_ctx* c, int64_t n, hipStream_t s, uint32_t& gen0, int 
   return PIMC_OK;
 }
 
-// Statistics staging chunk: the LDS left after the kernel's other buffers.
-int64_t stage_room(int NT, int K, bool fp64) {
-  const size_t base = pimc::sweep_smem_bytes(NT, K, fp64, 0) + pimc::LDS_STATIC_RESERVE;
-  if (base >= pimc::LDS_BYTES) return 0;
-  const size_t ts = fp64 ? 8 : 4;
-  return std::min<int64_t>((int64_t)NT * K + 1, (int64_t)((pimc::LDS_BYTES - base) / (4 * ts)));
-}
-
-// Launch shape of the sweep kernel for windows of up to maxM steps: sites per
-// thread K, threads NT and time tiles T (workgroups per window, tiles of
-// S = NT K sites with (T-1) S < M <= T S).  Automatic choice: one workgroup
-// per window with the smallest K that keeps it within 256 threads (one wave
-// per SIMD, no register spills), else any single-workgroup shape; windows too
-// long for one workgroup are cut into tiles of 256 threads.
+// Launch shape for windows of up to maxM steps under the context's tiling
+// settings (choose_sweep_shape); returns K, 0 when no shape fits.
 int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles, int& NT, int& stage, int& T) {
-  // K = 2 (FP32 only) is never the automatic choice: it is a tuning option
-  // for windows cut into many tiles, where it halves the sites per thread
-  static const int cand32[] = {4, 8, 16, 2};
-  // FP64 runs only in the spill-free shape (4 sites per thread, at most 256
-  // threads): the wider FP64 shapes spill about 1 KB per thread to scratch,
-  // and one of them (8 sites x 512 threads, M = 4096) faulted the GPU once
-  // without an identified cause, so they are not launched
-  static const int cand64[] = {4};
-  const int* cand = fp64 ? cand64 : cand32;
-  const int nc = fp64 ? 1 : (ctx->tile_K == 2 ? 4 : 3);
-  const int want_T = allow_tiles ? ctx->tiles : 1;
-  if (want_T <= 1) {
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i < nc; ++i) {
-        const int K = cand[i];
-        if (ctx->tile_K && ctx->tile_K != K) continue;
-        const int64_t need = (maxM + K - 1) / K;
-        const int64_t nt = std::max<int64_t>(64, (need + 63) / 64 * 64);
-        // wide single-workgroup shapes (more than 256 threads) spill to
-        // scratch: FP64 never uses them, and an FP32 window that may be cut
-        // into time tiles (automatic choice of pimc_sweep) is tiled instead
-        if (pass == 1 && (fp64 || (allow_tiles && want_T == 0))) continue;
-        const int64_t lim = pass == 0 ? 256 : pimc::sweep_max_threads(fp64, K);
-        if (nt > lim) continue;
-        const int64_t st = stage_room((int)nt, K, fp64);
-        if (st < 64) continue;
-        NT = (int)nt;
-        stage = (int)st;
-        T = 1;
-        return K;
-      }
-    }
-    if (want_T == 1 || !allow_tiles) return 0;
-  }
-  // FP64 windows are never cut into time tiles: that launch path faulted
-  // once on a 16-tile FP64 window without an identified cause, so it is
-  // refused here (FP64 is the small-window reference mode)
-  if (fp64) return 0;
-  // tiled: the requested T, or the fewest tiles of at most 256 threads
-  for (int Tt = want_T > 1 ? want_T : 2; Tt <= MAX_TILES; ++Tt) {
-    for (int i = 0; i < nc; ++i) {
-      const int K = cand[i];
-      if (ctx->tile_K && ctx->tile_K != K) continue;
-      for (int nt = 256; nt >= 64; nt -= 64) {
-        const int64_t S = (int64_t)nt * K;
-        if (!((Tt - 1) * S < maxM && maxM <= Tt * S)) continue;
-        const int64_t st = stage_room(nt, K, fp64);
-        if (st < 64) continue;
-        NT = nt;
-        stage = (int)st;
-        T = Tt;
-        return K;
-      }
-    }
-    if (want_T > 1) return 0;
-  }
-  return 0;
+  const pimc::SweepShape sh = pimc::choose_sweep_shape(maxM, fp64, allow_tiles, ctx->tile_K, ctx->tiles);
+  if (!sh.K) return 0;
+  NT = sh.NT;
+  stage = sh.stage;
+  T = sh.T;
+  return sh.K;
 }
 
 // Per-batch sums: the statistics samples one call takes (sweeps k0 .. k0+n-1
@@ -340,7 +274,7 @@ int pimc_ctx_create(pimc_ctx** out, int device) {
   if (const char* e = std::getenv("PIMC_TILE_K")) c->tile_K = std::atoi(e);
   if (const char* e = std::getenv("PIMC_NO_GRAPHS")) c->no_graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PIMC_BATCH_UNIFORM_K")) c->uniform_batch_K = std::atoi(e) != 0;
-  bool ok = ensure_tilespace(c, MAX_TILES, 4) == PIMC_OK;
+  bool ok = ensure_tilespace(c, pimc::MAX_TILES, 4) == PIMC_OK;
   int khz = 0;
   ok = ok && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0;
   if (!ok) {
@@ -381,7 +315,7 @@ int pimc_set_sweep_tile(pimc_ctx* ctx, int K) {
 }
 
 int pimc_set_sweep_tiles(pimc_ctx* ctx, int T) {
-  if (!ctx || T < 0 || T > MAX_TILES) return PIMC_ERR_ARG;
+  if (!ctx || T < 0 || T > pimc::MAX_TILES) return PIMC_ERR_ARG;
   ctx->tiles = T;
   return PIMC_OK;
 }
@@ -699,34 +633,22 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   if (n_sweeps == 0) return PIMC_OK;
   const int B = b->B;
   if (b->offsets[0] != 0) return PIMC_ERR_ARG;
-  int64_t maxM = 0;
   std::vector<int64_t> Ms(B);
   for (int i = 0; i < B; ++i) {
     const int64_t Mi = b->offsets[i + 1] - b->offsets[i] - 1;
     if (Mi < 1 || Mi >= (1ll << 30)) return PIMC_ERR_ARG;
     Ms[i] = Mi;
-    maxM = std::max(maxM, Mi);
   }
   pimc::SweepArgs a;
   std::memset(&a, 0, sizeof(a));
   int r = model_args(model, a.m);
   if (r) return r;
   const bool fp64 = b->prec == PIMC_FP64;
-  int NT = 0, stage = 0, T = 1;
-  int K = 0;
-  // Time tiles (set_sweep_tiles > 1) apply when every window of the batch
+  // time tiles (set_sweep_tiles > 1) apply when every window of the batch
   // needs exactly that many tiles of the chosen shape; otherwise one
-  // workgroup per window.
-  if (ctx->tiles > 1 && !fp64) {
-    K = choose_shape(ctx, maxM, fp64, true, NT, stage, T);
-    const int64_t S = (int64_t)NT * K;
-    for (int i = 0; K && i < B; ++i)
-      if (!((T - 1) * S < Ms[i] && Ms[i] <= T * S)) K = 0;
-  }
-  if (!K) {
-    T = 1;
-    K = choose_shape(ctx, maxM, fp64, false, NT, stage, T);
-  }
+  // workgroup per window
+  const pimc::SweepShape sh = pimc::choose_batch_shape(Ms.data(), B, fp64, ctx->tile_K, ctx->tiles);
+  const int K = sh.K, NT = sh.NT, stage = sh.stage, T = sh.T;
   if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);
   a.stage = stage;
@@ -765,17 +687,7 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   const bool perK = T == 1 && !fp64 && K == 16 && !ctx->uniform_batch_K;
   if (perK && ctx->blockK_NT != NT) {
     std::vector<int8_t> bk(B);
-    for (int i = 0; i < B; ++i) {
-      const int64_t Mi = Ms[order[i]];
-      int kw = 16;
-      for (int c : {4, 8, 12}) {
-        if ((int64_t)c * NT >= Mi) {
-          kw = c;
-          break;
-        }
-      }
-      bk[i] = (int8_t)kw;
-    }
+    for (int i = 0; i < B; ++i) bk[i] = (int8_t)pimc::batch_block_K(Ms[order[i]], NT);
     if ((r = hip_ok(hipMemcpyAsync(ctx->blockK, bk.data(), B * sizeof(int8_t), hipMemcpyHostToDevice, s))))
       return r;
     if ((r = hip_ok(hipStreamSynchronize(s)))) return r;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "device.hpp"
+#include "layout.hpp"
 
 namespace pimc {
 
@@ -58,8 +59,8 @@ struct SweepArgs {
   // time tiles (tiles == 1: a window is one workgroup, no global memory sync)
   int32_t tiles;
   int32_t ngroups;     // number of windows in the launch
-  void* halo;          // [ngroups*tiles][2][16] generation words: first / last boundary site
-  void* wpart;         // [2][ngroups][tiles][70] generation words: partial sums of the parameter statistics
+  void* halo;          // [ngroups*tiles][2][SLOT_WORDS] generation words: first / last boundary site
+  void* wpart;         // [2][ngroups][tiles][2 NRED] generation words: partial sums of the parameter statistics
   uint64_t* tsync;     // [ngroups*tiles] generation words: a tile's entry (payload: its entry check failed)
   uint32_t gen0;       // exchange generations of this call are gen0 + 1 .. gen0 + n_sweeps + 2
   uint64_t spin_ticks; // wall-clock ticks a wait may last
@@ -75,10 +76,6 @@ struct SweepArgs {
   int32_t* ip_cntp;    // [7] accepted parameter moves since the last adjustment (in/out)
 };
 
-size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage);
-constexpr size_t LDS_BYTES = 160 * 1024;       // LDS per CU on gfx950
-constexpr size_t LDS_STATIC_RESERVE = 1024;    // kept free for the kernels' static LDS
-int sweep_max_threads(bool fp64, int K);
 // ext: 0 the plain kernels; 1 the extended kernels (initialization phase,
 // kinetic constants, exact draws); 2 the exact-draw kernels.  Extended
 // kernels run in shapes of at most 256 threads and record the parameter and

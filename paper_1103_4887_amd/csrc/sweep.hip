@@ -33,8 +33,6 @@ namespace pimc {
 
 namespace {
 
-constexpr int NRED = 35;  // 7 (s) + 28 (upper triangle of G)
-
 template <typename T>
 struct Nb {  // a neighbour site: state and cached F
   T x[4];
@@ -190,7 +188,6 @@ __device__ __forceinline__ void lds_get(const Consts<T>& C, const T* slot, T I, 
 // never overwritten by a later generation before its reader has consumed it
 // (boundary sites: the writer needs the reader's progress first; partial
 // sums: double-buffered by sweep parity).
-constexpr int SLOT_WORDS = 16;   // one site: 7 values, two words each in FP64
 
 __device__ __forceinline__ uint64_t gen_word(uint32_t gen, uint32_t payload) {
   return ((uint64_t)gen << 32) | payload;
@@ -578,13 +575,6 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(SweepArgs a) {
 #include "sweep_body.inc"
 }
 
-size_t sweep_smem_bytes(int NT, int K, bool fp64, int stage) {
-  const size_t ts = fp64 ? 8 : 4;
-  const size_t NW = (size_t)NT / 64;
-  return (size_t)NT * 8 * ts * 2 + (size_t)2 * (NT * K + 2) * ts + (NRED * 4 * NW + NRED + 40) * sizeof(double) +
-         16 * sizeof(int) + (size_t)stage * 4 * ts;
-}
-
 __global__ void zero_u32_kernel(uint32_t* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -715,14 +705,6 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
     case 16: return launch_pick<float, 16, 512>(a, dbg, ext, nblocks, NT, sm, s);
     default: return PIMC_ERR_UNSUPPORTED;
   }
-}
-
-int sweep_max_threads(bool fp64, int K) {
-  if (fp64) return K == 4 ? 256 : 0;
-  if (K == 2) return 256;
-  if (K == 4) return 1024;
-  if (K == 8 || (!fp64 && K == 16)) return 512;
-  return 0;
 }
 
 }  // namespace pimc

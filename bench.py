@@ -226,7 +226,18 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
         posterior statistics."""
         bm = fresh()
         t0 = time.perf_counter()
-        P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=0, w=w, n_sweeps=50, flags=flags)
+        try:
+            P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=0, w=w, n_sweeps=50, flags=flags)
+            shape_f = shape
+        except P._lib.PimcError as e:
+            # the extended kernels (exact draws) take the shapes of at most 4
+            # sites per thread and 256 threads: tune among those
+            if e.status != P._lib.PIMC_ERR_UNSUPPORTED:
+                raise
+            shape_f = autotune.tune_batch(ctx, spec, bm, w, flags=flags)
+            bm = fresh()
+            t0 = time.perf_counter()
+            P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=0, w=w, n_sweeps=50, flags=flags)
         assert ctx.sync() == 0
         t_probe = time.perf_counter()
         P.pimc_run_batch(ctx, spec, bm, seed=prob.seed + seed_off, sweep0=50, w=w, n_sweeps=200, flags=flags)
@@ -245,7 +256,9 @@ def hmc_vs_sweep(ctx, prob, chains: int, budget_s: float, equilibrate_s: float, 
         del sm.ptrace
         ess_m, mean_m, mcse_m = _post_stats(tr_m, mask)
         acc_m = sm.acc.cpu().numpy()
-        rec = {"chains": B, "launch": {"K": shape[0], "tiles": shape[1]}, "sweeps": n_m, "trace_stride": stride,
+        if shape_f is not shape:
+            autotune.tune_batch(ctx, spec, start, w)   # back to the batch's own shape
+        rec = {"chains": B, "launch": {"K": shape_f[0], "tiles": shape_f[1]}, "sweeps": n_m, "trace_stride": stride,
                "wall_s": wall_m, "us_per_sweep": per_sweep * 1e6,
                "site_updates_per_s": B * (prob.M + 1) * n_m / wall_m,
                "param_ess_per_s": float(ess_m.min() / wall_m),

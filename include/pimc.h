@@ -65,9 +65,10 @@ enum { PIMC_PROP_GAUSS = 0, PIMC_PROP_UNIFORM = 1 }; /* proposal law (Fig. 1 ste
  * with word 0 of the parameter's Philox block.  It changes the chain, so it
  * is off unless asked for; acceptance counters then count finite draws.
  * Runs in the launch shapes of at most 256 threads per workgroup and at most
- * 8 sites per thread (others, among them the automatic single-workgroup
- * shape of windows of 2049 to 4096 steps, return PIMC_ERR_UNSUPPORTED; such
- * windows run with time tiles, see pimc_set_sweep_tiles). */
+ * 4 sites per thread: the automatic choice cuts windows longer than 1024
+ * steps into time tiles of such shapes, and a shape forced wider (see
+ * pimc_set_sweep_tile, pimc_set_sweep_tiles) returns PIMC_ERR_UNSUPPORTED
+ * before anything is launched. */
 enum { PIMC_STATES = 1, PIMC_PARAMS = 2, PIMC_GIBBS = 4, PIMC_KINETIC = 8 };
 /* PIMC_KINETIC (pimc_sweep / pimc_sweep_init on a path with `kin` set): after
  * the parameters, each Table 1 constant selected by model->k_mask, in the
@@ -77,7 +78,8 @@ enum { PIMC_STATES = 1, PIMC_PARAMS = 2, PIMC_GIBBS = 4, PIMC_KINETIC = 8 };
  * enter the gate equations nonlinearly, so each move is a full pass over the
  * path with the change of A summed in FP64 over all links (the direct form of
  * Section 4.1; Section 5.1 notes all the model's constants can be estimated
- * this way).  Runs in the launch shapes of at most 256 threads. */
+ * this way).  Runs in the launch shapes of at most 256 threads and at most 4
+ * sites per thread, as PIMC_GIBBS. */
 
 /* Most sweeps one call may run when its windows are cut into time tiles
  * (longer runs are split into several calls by the caller). */
@@ -322,8 +324,9 @@ typedef struct {
 
 /* pimc_sweep with the initialization phase of Section 4.2 (annealing of beta
  * and adjustment of the step sizes, see pimc_init_phase).  Runs in the launch
- * shapes of at most 256 threads per workgroup (the automatic choice, or time
- * tiles); others return PIMC_ERR_UNSUPPORTED.  No debug record. */
+ * shapes of at most 256 threads per workgroup and at most 4 sites per thread
+ * (the automatic choice, or time tiles); others return PIMC_ERR_UNSUPPORTED.
+ * No debug record. */
 int pimc_sweep_init(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng rng,
                     const double* w, int64_t n_sweeps, int32_t flags, const pimc_init_phase* init,
                     const pimc_stats* stats, void* stream);

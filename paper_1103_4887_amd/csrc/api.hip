@@ -210,8 +210,9 @@ int tile_generations(pimc_ctx* c, int64_t n, hipStream_t s, uint32_t& gen0, int 
 
 // Launch shape for windows of up to maxM steps under the context's tiling
 // settings (choose_sweep_shape); returns K, 0 when no shape fits.
-int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles, int& NT, int& stage, int& T) {
-  const pimc::SweepShape sh = pimc::choose_sweep_shape(maxM, fp64, allow_tiles, ctx->tile_K, ctx->tiles);
+int choose_shape(const pimc_ctx* ctx, int64_t maxM, bool fp64, bool allow_tiles, int& NT, int& stage, int& T,
+                 bool ext = false) {
+  const pimc::SweepShape sh = pimc::choose_sweep_shape(maxM, fp64, allow_tiles, ctx->tile_K, ctx->tiles, ext);
   if (!sh.K) return 0;
   NT = sh.NT;
   stage = sh.stage;
@@ -490,7 +491,12 @@ int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   const bool fp64 = path->prec == PIMC_FP64;
   int NT = 0, stage = 0, T = 1;
   if (path->M >= (1ll << 30)) return PIMC_ERR_UNSUPPORTED;
-  const int K = choose_shape(ctx, path->M, fp64, true, NT, stage, T);
+  // the initialization phase and kinetic constants run in the extended
+  // kernels (which draw exactly too), exact parameter draws alone in the
+  // exact-draw kernels: shapes of at most 256 threads and 4 sites per thread
+  const bool kinetic = (flags & PIMC_KINETIC) != 0;
+  const int ext = (ip || kinetic) ? 1 : ((flags & PIMC_GIBBS) ? 2 : 0);
+  const int K = choose_shape(ctx, path->M, fp64, true, NT, stage, T, ext != 0);
   if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);
   a.stage = stage;
@@ -527,7 +533,6 @@ int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
   fill_debug(a, debug);
   a.err = ctx->err;
   if (hipSetDevice(ctx->device) != hipSuccess) return PIMC_ERR_HIP;
-  const bool kinetic = (flags & PIMC_KINETIC) != 0;
   if (kinetic && !path->kin) return PIMC_ERR_ARG;
   a.kin = path->kin;
   if (debug) {
@@ -535,10 +540,6 @@ int sweep_impl(pimc_ctx* ctx, const pimc_model* model, pimc_path* path, pimc_rng
     a.dbg_kdA = debug->kdA;
     a.dbg_kacc = debug->kaccept;
   }
-  // the initialization phase and kinetic constants run in the extended
-  // kernels (which draw exactly too), exact parameter draws alone in the
-  // exact-draw kernels (shapes of at most 256 threads)
-  const int ext = (ip || kinetic) ? 1 : ((flags & PIMC_GIBBS) ? 2 : 0);
   if (ext && NT > 256) return PIMC_ERR_UNSUPPORTED;
   if (ip && (r = init_args(ip, a))) return r;
   // all-reduces between the tiles per sweep: the parameter statistics and
@@ -647,7 +648,8 @@ int pimc_run_batch(pimc_ctx* ctx, const pimc_model* model, const pimc_batch* b, 
   // time tiles (set_sweep_tiles > 1) apply when every window of the batch
   // needs exactly that many tiles of the chosen shape; otherwise one
   // workgroup per window
-  const pimc::SweepShape sh = pimc::choose_batch_shape(Ms.data(), B, fp64, ctx->tile_K, ctx->tiles);
+  const pimc::SweepShape sh =
+      pimc::choose_batch_shape(Ms.data(), B, fp64, ctx->tile_K, ctx->tiles, (flags & PIMC_GIBBS) != 0);
   const int K = sh.K, NT = sh.NT, stage = sh.stage, T = sh.T;
   if (!K) return PIMC_ERR_UNSUPPORTED;
   fill_consts(a);

@@ -139,8 +139,11 @@ struct SweepShape {
 // Automatic choice: one workgroup per window with the smallest K that keeps
 // it within 256 threads (one wave per SIMD, no register spills), else (when
 // tiles may not be used) any single-workgroup shape; windows too long for one
-// 256-thread workgroup are cut into tiles of at most 256 threads.
-inline SweepShape choose_sweep_shape(int64_t maxM, bool fp64, bool allow_tiles, int tile_K, int tiles) {
+// 256-thread workgroup are cut into tiles of at most 256 threads.  ext: the
+// shape of an extended kernel (exact draws, initialization phase, Table 1
+// constants), at most 256 threads and at most 4 sites per thread.
+inline SweepShape choose_sweep_shape(int64_t maxM, bool fp64, bool allow_tiles, int tile_K, int tiles,
+                                     bool ext = false) {
   SweepShape sh{0, 0, 0, 1};
   // K = 2 (FP32 only) is never the automatic choice: it is a tuning option
   // for windows cut into many tiles, where it halves the sites per thread
@@ -157,13 +160,13 @@ inline SweepShape choose_sweep_shape(int64_t maxM, bool fp64, bool allow_tiles, 
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i < nc; ++i) {
         const int K = cand[i];
-        if (tile_K && tile_K != K) continue;
+        if ((tile_K && tile_K != K) || (ext && K > 4)) continue;
         const int64_t need = (maxM + K - 1) / K;
         const int64_t nt = need > 64 ? (need + 63) / 64 * 64 : 64;
         // wide single-workgroup shapes (more than 256 threads) spill to
         // scratch: FP64 never uses them, and an FP32 window that may be cut
         // into time tiles (automatic choice) is tiled instead
-        if (pass == 1 && (fp64 || (allow_tiles && want_T == 0))) continue;
+        if (pass == 1 && (fp64 || ext || (allow_tiles && want_T == 0))) continue;
         const int64_t lim = pass == 0 ? 256 : sweep_max_threads(fp64, K);
         if (nt > lim) continue;
         const int64_t st = stage_room((int)nt, K, fp64);
@@ -183,7 +186,7 @@ inline SweepShape choose_sweep_shape(int64_t maxM, bool fp64, bool allow_tiles, 
   for (int Tt = want_T > 1 ? want_T : 2; Tt <= MAX_TILES; ++Tt) {
     for (int i = 0; i < nc; ++i) {
       const int K = cand[i];
-      if (tile_K && tile_K != K) continue;
+      if ((tile_K && tile_K != K) || (ext && K > 4)) continue;
       for (int nt = 256; nt >= 64; nt -= 64) {
         const int64_t S = (int64_t)nt * K;
         if (!((Tt - 1) * S < maxM && maxM <= Tt * S)) continue;
@@ -204,17 +207,17 @@ inline SweepShape choose_sweep_shape(int64_t maxM, bool fp64, bool allow_tiles, 
 // Launch shape of a batch of B windows of Ms[i] steps: time tiles (tiles > 1,
 // FP32) when every window needs exactly that many tiles of the shape chosen
 // for the longest, else one workgroup per window.
-inline SweepShape choose_batch_shape(const int64_t* Ms, int B, bool fp64, int tile_K, int tiles) {
+inline SweepShape choose_batch_shape(const int64_t* Ms, int B, bool fp64, int tile_K, int tiles, bool ext = false) {
   int64_t maxM = 0;
   for (int i = 0; i < B; ++i) maxM = Ms[i] > maxM ? Ms[i] : maxM;
   SweepShape sh{0, 0, 0, 1};
   if (tiles > 1 && !fp64) {
-    sh = choose_sweep_shape(maxM, fp64, true, tile_K, tiles);
+    sh = choose_sweep_shape(maxM, fp64, true, tile_K, tiles, ext);
     const int64_t S = (int64_t)sh.NT * sh.K;
     for (int i = 0; sh.K && i < B; ++i)
       if (!((sh.T - 1) * S < Ms[i] && Ms[i] <= sh.T * S)) sh.K = 0;
   }
-  if (!sh.K) sh = choose_sweep_shape(maxM, fp64, false, tile_K, tiles);
+  if (!sh.K) sh = choose_sweep_shape(maxM, fp64, false, tile_K, tiles, ext);
   return sh;
 }
 

@@ -657,12 +657,12 @@ static int launch_checked(Kern k, int nblocks, int NT, size_t sm, hipStream_t s,
 
 // One launch shape: an extended kernel when asked for (ext 1: the
 // initialization phase, kinetic constants and exact draws; ext 2: exact
-// draws only; one wave per SIMD shapes only), the debug kernel when a
-// debug record is, else the plain kernel.
+// draws only; one wave per SIMD and at most 4 sites per thread), the debug
+// kernel when a debug record is, else the plain kernel.
 template <typename T, int K, int MAXT>
 static int launch_shape(const SweepArgs& a, bool dbg, int ext, int nblocks, int NT, size_t sm, hipStream_t s) {
   if (ext) {
-    if constexpr (MAXT <= 256) {
+    if constexpr (MAXT <= 256 && K <= 4) {
       if (ext == 2) return launch_checked(sweep_kernel<T, K, MAXT, false, 2>, nblocks, NT, sm, s, a);
       return launch_checked(sweep_kernel<T, K, MAXT, false, 1>, nblocks, NT, sm, s, a);
     } else {
@@ -688,10 +688,12 @@ int launch_sweep(const SweepArgs& a, bool fp64, int K, int nblocks, int NT, hipS
   const bool dbg = a.dbg_xprop || a.dbg_dA || a.dbg_acc || a.dbg_pprop || a.dbg_pdA || a.dbg_pacc;
   // the extended kernels record the parameter and kinetic moves, not sites
   if (ext && (a.dbg_xprop || a.dbg_dA || a.dbg_acc)) return PIMC_ERR_UNSUPPORTED;
-  // exact parameter draws are not launched in the extended kernels of 16
-  // sites per thread: a test run of that launch was followed by a GPU fault
-  // whose cause is not identified
-  if (ext && K == 16 && (a.flags & PIMC_GIBBS)) return PIMC_ERR_UNSUPPORTED;
+  // the extended kernels run with at most 4 sites per thread: two test runs
+  // that launched them with 16 (exact draws, then the initialization phase,
+  // each a single workgroup of 256 threads on a 4096-step window) were
+  // followed by GPU faults whose cause is not identified, and the shapes of
+  // 2 and 4 sites per thread are the ones their tests have run throughout
+  if (ext && K > 4) return PIMC_ERR_UNSUPPORTED;
   if (fp64) {
     if (K != 4 || NT > 256) return PIMC_ERR_UNSUPPORTED;   // wide FP64 shapes are not launched
     return launch_shape<double, 4, 256>(a, dbg, ext, nblocks, NT, sm, s);

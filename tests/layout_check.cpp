@@ -23,7 +23,8 @@
 // reduction, all-reduce over tiles, kinetic moves, statistics, write-back.
 //
 // Input (stdin), one case a line:
-//   single <M> <fp64> <tile_K> <tiles>        one window, shape as pimc_sweep picks it
+//   single <M> <fp64> <tile_K> <tiles> [ext]  one window, shape as pimc_sweep picks it
+//                                             (ext 1: for an extended kernel)
 //   batch <fp64> <tile_K> <tiles> <uniK> <M1> ...  a batch, shape as pimc_run_batch picks it
 //                                             (uniK 1: every window with the launch's K)
 //   forced <M> <fp64> <K> <NT> <T>            one window in the given shape, checked
@@ -82,7 +83,7 @@ bool launch_accepted(const Launch& L, int ext) {
   if (sm + LDS_STATIC_RESERVE > LDS_BYTES || L.NT > sweep_max_threads(L.fp64, L.K)) return false;
   if (L.fp64 && (L.K != 4 || L.NT > 256)) return false;
   if (!L.fp64 && L.K == 2 && L.NT > 256) return false;
-  if (ext && L.NT > 256) return false;
+  if (ext && (L.NT > 256 || L.K > 4)) return false;
   return true;
 }
 
@@ -324,13 +325,14 @@ int main() {
     std::string kind;
     if (!(in >> kind) || kind[0] == '#') continue;
     Launch L{};
-    int fp64 = 0, tile_K = 0, tiles = 0, uniK = 0;
+    int fp64 = 0, tile_K = 0, tiles = 0, uniK = 0, ext = 0;
     SweepShape sh{};
     if (kind == "single") {
       int64_t M;
       in >> M >> fp64 >> tile_K >> tiles;
+      if (!(in >> ext)) ext = 0;
       L.Ms = {M};
-      sh = choose_sweep_shape(M, fp64 != 0, true, tile_K, tiles);
+      sh = choose_sweep_shape(M, fp64 != 0, true, tile_K, tiles, ext != 0);
       L.batch = false;
     } else if (kind == "batch") {
       in >> fp64 >> tile_K >> tiles >> uniK;
@@ -356,7 +358,7 @@ int main() {
     L.NT = sh.NT;
     L.T = sh.T;
     L.stage = sh.stage;
-    const bool accepted = sh.K && launch_accepted(L, 0);
+    const bool accepted = sh.K && launch_accepted(L, ext);
     if (!accepted) ++refused;
     if (!sh.K || (!accepted && kind != "forced")) {
       std::printf("refused %s\n", g_case.c_str());

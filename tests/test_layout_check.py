@@ -128,6 +128,26 @@ def test_ragged_windows(checker):
     assert "FAIL" not in out
 
 
+def test_extended_kernel_shapes(checker):
+    """Exact draws, the initialization phase and the Table 1 constants run in
+    shapes of at most 4 sites per thread and 256 threads: the automatic
+    choice cuts longer windows into time tiles, and a forced wider shape is
+    refused."""
+    lines = [f"single {M} {p} 0 0 1" for M in (96, 200, 257, 300, 1024, 2048, 2049, 4096) for p in (0, 1)]
+    lines += ["single 4096 0 2 16 1", "single 4096 0 0 4 1", "single 4096 0 0 8 1",
+              "single 4096 0 16 1 1", "single 4096 0 8 1 1", "single 4096 0 4 1 1"]
+    rc, out = run(checker, lines)
+    assert rc == 0, out
+    ok = {ln.split(" K=")[0][3:]: ln for ln in out.splitlines() if ln.startswith("ok ")}
+    for M in (96, 200, 257, 300, 1024, 2048, 2049, 4096):
+        case = f"single {M} 0 0 0 1"
+        assert case in ok and (" K=4 " in ok[case] or " K=2 " in ok[case]), out
+    assert "T=4" in ok["single 4096 0 0 0 1"], out          # 4 tiles of 256 threads x 4 sites
+    for case in ("single 4096 0 16 1 1", "single 4096 0 8 1 1", "single 4096 0 4 1 1",
+                 "single 2049 1 0 0 1", "single 4096 1 0 0 1"):
+        assert f"refused {case}" in out, out
+
+
 def test_detects_a_layout_too_small(checker):
     # 2 tiles of 64 threads x 4 sites cannot hold 5001 sites
     rc, out = run(checker, ["forced 5000 0 4 64 2"])

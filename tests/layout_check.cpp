@@ -158,8 +158,6 @@ void check_launch(const Launch& L) {
         require(n >= lo && n <= hi, "(y, I) read of a site not loaded", n, lo, hi);
       };
       for (int n = lo; n <= hi; ++n) {
-        // the fill issues K + 1 loads per thread, site lo + t + r NT
-        require(n - lo < (long long)NT * (Kb + 1), "(y, I) site beyond the fill's K + 1 rounds", n, lo);
         lyb(n, 0, "lyi store y");
         lyb(n, 1, "lyi store I");
         in_range("y/I global read", base + n, total_sites, n);

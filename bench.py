@@ -66,10 +66,11 @@ def parse():
 
 
 def kernel_source_sha256() -> str:
-    """sha256 over the sweep kernel's source files (sweep.hip, then sweep_body.inc)."""
+    """sha256 over the sweep kernel's source files (sweep.hip, sweep_body.inc,
+    then layout.hpp)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("sweep.hip", "sweep_body.inc"):
+    for name in ("sweep.hip", "sweep_body.inc", "layout.hpp"):
         with open(os.path.join(ROOT, "paper_1103_4887_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

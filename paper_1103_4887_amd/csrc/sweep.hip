@@ -342,6 +342,35 @@ __device__ __forceinline__ void link_stats(const double (&th)[7], double h, cons
     for (int b = a; b < 7; ++b) acc[7 + sym7(a, b)] += phi[a] * phi[b];
 }
 
+// The values LO .. LO + N - 1 of link_stats (the same sums, term for term),
+// for shapes whose registers cannot hold all 35 sums beside the path.
+template <int LO, int N>
+__device__ __forceinline__ void link_stats_part(const double (&th)[7], double h, const Feat& l, const Feat& r,
+                                                double (&acc)[N]) {
+  double phi[7];
+  phi[0] = h * (r.I + l.I);
+  phi[1] = -h * (r.m3h * r.V + l.m3h * l.V);
+  phi[2] = h * (r.m3h + l.m3h);
+  phi[3] = -h * (r.n4 * r.V + l.n4 * l.V);
+  phi[4] = h * (r.n4 + l.n4);
+  phi[5] = -h * (r.V + l.V);
+  phi[6] = 2.0 * h;
+  double thphi = 0.0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) thphi += th[q] * phi[q];
+  const double e = (r.V - l.V) - thphi;
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    if (q >= LO && q < LO + N) acc[q - LO] += phi[q] * e;
+#pragma unroll
+  for (int a = 0; a < 7; ++a)
+#pragma unroll
+    for (int b = a; b < 7; ++b) {
+      const int i = 7 + sym7(a, b);
+      if (i >= LO && i < LO + N) acc[i - LO] += phi[a] * phi[b];
+    }
+}
+
 // theta components moved by a change dp of parameter l (0-based), with the
 // current parameters p:  theta = (p1, p2, p2 p3, p4, p4 p5, p6, p6 p7).
 template <int L>

@@ -37,8 +37,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock
 # WRITE_SIZE runs calibrated against a plain copy (profiles/ holds the
 # summary).  They belong to one version of the kernel source: when the source
 # hash differs, the traffic is reported as unknown.
-TRAFFIC = {"sweep_source_sha256": "2b30e4a8def8909ec14576c89f85bfb60763248dc0debebee2b91a73e8a474d4",
-           "launch": (2, 16), "fetch_bytes_per_sweep": 80.8e3, "write_bytes_per_sweep": 16.6e3}
+TRAFFIC = {"sweep_source_sha256": "b997400030c0ef7fd32ed63f2191250528a169fbf8cab0a395141e4b0bd8d668",
+           "launch": (2, 16), "fetch_bytes_per_sweep": 80.3e3, "write_bytes_per_sweep": 16.6e3}
 
 
 def parse():

@@ -360,7 +360,9 @@ def _timed(stream, fn):
     marshalling, the launch) overlaps it, as it does in any caller that keeps
     the device busy: the events then time the device work of the call, all of
     it, without the idle gap of a device waiting for its first launch.  The
-    wall time (host clock, delay included) is reported beside it."""
+    delay (about 1 ms) also brings the device out of any idle clock state
+    before the timed work starts.  The wall time (host clock, delay
+    included) is reported beside it."""
     import torch
 
     torch.cuda.synchronize()
@@ -368,7 +370,7 @@ def _timed(stream, fn):
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        torch.cuda._sleep(200000)
+        torch.cuda._sleep(2000000)
     ev0.record(stream)
     r = fn()
     ev1.record(stream)

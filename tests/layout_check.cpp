@@ -209,6 +209,20 @@ void check_launch(const Launch& L) {
           for (int sl = 0; sl < 4; ++sl)
             in_range("lred wave totals", (long long)wv * 4 * ((NRED + 3) / 4) + 4 * j + sl, n_lred, t);
         in_range("lred kinetic", (long long)wv * 4 + 3, n_lred, t);
+        if (NT > 256) {
+          // wide shapes: the two halves of the sums (values 0..17, 18..34)
+          // are folded and stored separately, each below its own count
+          for (int lo : {0, 18}) {
+            const int n = lo == 0 ? 18 : NRED - 18;
+            for (int j = 0; j < (n + 3) / 4; ++j)
+              for (int sl = 0; sl < 4; ++sl)
+                if (4 * j + sl < n) {
+                  const long long pos = lo + 4 * j + sl;
+                  require(pos < NRED, "half-sum slot beyond the wave's values", pos);
+                  in_range("lred half-sum totals", (long long)wv * 4 * ((NRED + 3) / 4) + pos, n_lred, t);
+                }
+          }
+        }
         if (t < NRED) in_range("lstat", t, NRED);
         if (t < 2 * NRED) in_range("lstat words", t >> 1, NRED);
         if (t < 16) in_range("lcnt clear", t, LCNT);
